@@ -1,0 +1,132 @@
+/*
+ * lesmi: MI355X (gfx950) LES residual and time stepping for the filtered compressible
+ * Navier-Stokes equations on a structured curvilinear grid, after Junqueira-Junior,
+ * Yamouni, Azevedo & Wolf, "Large Eddy Simulations of Supersonic Jet Flows for
+ * Aeroacoustic Applications" (arXiv 2212.12365).
+ *
+ * Plain C ABI: host or device pointers and sizes only.
+ *
+ * Data layout. A grid has ni x nj x nk distinct nodes (periodic directions are not
+ * duplicated). Node (i,j,k) has offset n = i + ni*(j + nj*k). A conserved field q is five
+ * contiguous component planes q[c][n], c = 0..4 for (rho, rho u, rho v, rho w, e), FP64,
+ * in the paper's dimensionless units (density by rho_ref, velocity by a_ref, pressure and
+ * energy by rho_ref a_ref^2, length by L_ref, time by L_ref/a_ref). Directions 0,1,2 are
+ * xi (i), eta (j), zeta (k); for the jet these are axial, radial and azimuthal.
+ *
+ * Ownership. The caller owns every array passed in; the context owns the grid metrics,
+ * the Runge-Kutta stage buffers, the boundary data and the time-step scalar. No entry
+ * point other than les_init_grid and les_destroy allocates or frees memory.
+ *
+ * Streams. `stream` is a hipStream_t (NULL = the null stream). Every call except
+ * les_init_grid and les_destroy is asynchronous on that stream, and may be issued from
+ * one host thread at a time per context. les_step synchronises once, at its end, to read
+ * its status flag; les_diagnostics synchronises to return host values.
+ *
+ * Errors. Every call returns an les_status and never aborts; les_last_error() gives a
+ * message for the context's last failure.
+ */
+#ifndef LESMI_H
+#define LESMI_H
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct les_ctx les_ctx;
+
+typedef enum {
+  LES_OK = 0,
+  LES_EINVAL = -1,      /* bad argument or unsupported parameter set */
+  LES_ENOMEM = -2,      /* device allocation failed */
+  LES_EGRID = -3,       /* J^-1 <= 0 at an updated node (left-handed or folded grid) */
+  LES_EHIP = -4,        /* a HIP runtime call failed */
+  LES_ENONFINITE = -5,  /* non-finite value or non-positive density/pressure produced */
+  LES_ESTATE = -6       /* call not valid in the context's current state */
+} les_status;
+
+typedef enum {
+  LES_BC_PERIODIC = 0,
+  LES_BC_AXIS = 1,        /* jet centreline (j-) */
+  LES_BC_JET_INFLOW = 2,  /* jet entrance (i-) */
+  LES_BC_FARFIELD = 3,    /* Riemann-invariant far field (j+) */
+  LES_BC_EXIT = 4         /* exit plane (i+) */
+} les_bc;
+
+typedef enum { LES_FP64 = 0, LES_MIXED = 1 } les_precision;
+typedef enum { LES_SMAGORINSKY = 0, LES_MLP = 1 } les_closure;
+
+/* Problem parameters (paper: Dimensionless Formulation, LES formulation, Subgrid Scale
+ * Modeling, Spatial Discretization, Boundary Conditions). Supported boundary sets:
+ * all six faces periodic (a box), or the jet set {i-: JET_INFLOW, i+: EXIT, j-: AXIS,
+ * j+: FARFIELD, k: PERIODIC}. Each direction needs at least 4 nodes. */
+typedef struct {
+  int ni, nj, nk;
+  int bc[6];                  /* faces i-, i+, j-, j+, k-, k+ (les_bc) */
+  double period_shift[3][3];  /* [direction][x,y,z]: coordinate jump across a periodic wrap */
+  double gamma;               /* ratio of specific heats */
+  double prandtl;             /* molecular Prandtl number (0.72) */
+  double prandtl_sgs;         /* SGS Prandtl number (0.6) */
+  double re_acoustic;         /* rho_ref a_ref L_ref / mu_ref; 0 = no molecular viscosity */
+  double suth_s1;             /* Sutherland constant / reference temperature (110.4 K / T_ref) */
+  double cs;                  /* Smagorinsky constant */
+  double k2, k4;              /* Turkel-Vatsa dissipation constants (0.25, 0.016) */
+  double mach_jet;            /* jet exit velocity / a_ref */
+  double jet_radius;          /* entrance nodes with sqrt(y^2+z^2) <= jet_radius are jet */
+  double rho_inf, u_inf[3], p_inf;  /* free stream for the far field and exit */
+  int precision;              /* les_precision */
+  int closure;                /* les_closure */
+} les_params;
+
+/* Grid metrics (paper, Transformation of Coordinates): computes on the device
+ * S_d = J^-1 grad(xi_d) in conservative form and J^-1 = det(dx/dxi) from the node
+ * coordinates, and the boundary normals. `xyz` is a HOST array [3][nk][nj][ni] (x, y, z).
+ * Synchronous. Returns LES_EGRID if J^-1 <= 0 at an updated node (the context is still
+ * created so the caller may inspect it), LES_EINVAL for unsupported parameters. */
+int les_init_grid(const les_params* params, const double* xyz, les_ctx** out);
+
+/* Residual RHS_ijk of the semi-discrete system dQ/dt = -J RHS (paper, Spatial
+ * Discretization: central interface flux with Turkel-Vatsa artificial dissipation minus
+ * the viscous and subgrid fluxes, summed over the three directions). q and rhs are DEVICE
+ * arrays [5][N]. rhs is written at every node: 0 on boundary-condition nodes. */
+int les_residual(les_ctx* ctx, const double* q, double* rhs, void* stream);
+
+/* Advances q (DEVICE [5][N], in place) by nsteps steps of the five-stage Runge-Kutta
+ * scheme, alpha = (1/4, 1/6, 3/8, 1/2, 1) (paper, Time Marching Method), applying the
+ * boundary conditions after every stage. If cfl > 0 each step uses
+ * dt = cfl * min over updated nodes of J^-1 / sum_d (|S_d.u| + a|S_d|), computed on the
+ * device from the state at the start of the step; otherwise dt = dt_fixed. dt_last (HOST,
+ * may be NULL) receives the dt of the last step. q is expected to satisfy the boundary
+ * conditions on entry (see les_apply_bc). Returns LES_ENONFINITE if a non-finite value or
+ * non-positive density or pressure appeared; q then holds the failing state. */
+int les_step(les_ctx* ctx, double* q, int nsteps, double cfl, double dt_fixed,
+             double* dt_last, void* stream);
+
+/* Smagorinsky eddy viscosity mu_sgs = rho (C_s Delta)^2 (2 S_ij S_ij)^(1/2) at every node
+ * (paper, Subgrid Scale Viscosity), Delta = (J^-1)^(1/3), 0 where J^-1 <= 0. q DEVICE
+ * [5][N], mu_t DEVICE [N], in units of rho_ref a_ref L_ref. */
+int les_sgs_viscosity(les_ctx* ctx, const double* q, double* mu_t, void* stream);
+
+/* Sets the boundary-condition nodes of q (DEVICE [5][N], in place) from its updated nodes
+ * (paper, Boundary Conditions): far field, then centreline (azimuthal mean of the first
+ * ring), then entrance, then exit. A no-op for a periodic box. */
+int les_apply_bc(les_ctx* ctx, double* q, void* stream);
+
+/* Diagnostics over updated nodes, summed in a fixed order: out[0] = volume-weighted mean
+ * kinetic energy sum J^-1 rho|u|^2/2 / sum J^-1; out[1..5] = sum J^-1 Q_c. q DEVICE [5][N];
+ * out HOST [6]. Synchronises the stream. */
+int les_diagnostics(les_ctx* ctx, const double* q, double* out, void* stream);
+
+/* Copies the context's metrics to DEVICE arrays S [9][N] (S_d^c at index 3d + c) and
+ * jinv [N]; either may be NULL. */
+int les_get_metrics(les_ctx* ctx, double* S, double* jinv, void* stream);
+
+/* Number of nodes updated by the time integration (those not on a non-periodic face). */
+long long les_updated_nodes(const les_ctx* ctx);
+
+void les_destroy(les_ctx* ctx);
+const char* les_last_error(const les_ctx* ctx);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

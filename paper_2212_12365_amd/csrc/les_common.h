@@ -1,0 +1,74 @@
+// Shared host/device definitions of the lesmi library (gfx950).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+
+#include "../../include/lesmi.h"
+#include "les_device.h"
+
+namespace lesmi {
+
+// Grid extents, periodicity and derived sizes, passed by value to every kernel.
+struct Dims {
+  int n[3];
+  int per[3];
+  int jet;     // 1 for the jet boundary set, 0 for a periodic box
+  long long N; // nodes
+};
+
+__device__ __host__ __forceinline__ long long nid(const Dims& D, int i, int j, int k) {
+  return (long long)i + (long long)D.n[0] * ((long long)j + (long long)D.n[1] * k);
+}
+
+__device__ __host__ __forceinline__ bool is_updated(const Dims& D, int i, int j, int k) {
+  if (!D.per[0] && (i == 0 || i == D.n[0] - 1)) return false;
+  if (!D.per[1] && (j == 0 || j == D.n[1] - 1)) return false;
+  if (!D.per[2] && (k == 0 || k == D.n[2] - 1)) return false;
+  return true;
+}
+
+struct BcData {
+  double* nff;    // [3][ni*nk] far-field outward unit normal at j = nj-1
+  double* nin;    // [3][nj*nk] entrance outward unit normal at i = 0
+  double* nex;    // [3][nj*nk] exit outward unit normal at i = ni-1 (axis node: j = 1's)
+  int* jetmask;   // [nj*nk] entrance node lies inside the jet
+  double* axis;   // [5][ni] centreline means
+  double rho_inf, u_inf[3], p_inf, mach_jet;
+};
+
+}  // namespace lesmi
+
+struct les_ctx {
+  les_params params;
+  lesmi::Dims dims;
+  lesmi::Phys phys;
+  long long n_updated = 0;
+  int device = 0;
+  std::string err;
+
+  // Metrics (FP64): S[9][N], jinv[N], jac[N] = 1/jinv at updated nodes (0 elsewhere).
+  double* S = nullptr;
+  double* jinv = nullptr;
+  double* jac = nullptr;
+  lesmi::BcData bc{};
+
+  // Runge-Kutta stage buffers [5][N] each.
+  double* qa = nullptr;
+  double* qb = nullptr;
+
+  // Work arrays of the residual pipeline.
+  double* prim = nullptr;   // [7][N]: rho u v w p T mu
+  double* node = nullptr;   // [19][N]: dq[3][4], mut, lbar[3], nu[3]
+  double* flux = nullptr;   // [3][5][N] face fluxes
+  double* rhs = nullptr;    // [5][N]
+
+  // Scalars: dt, min-ratio bits, status flags, reduction partials.
+  double* d_dt = nullptr;
+  unsigned long long* d_minbits = nullptr;
+  int* d_flag = nullptr;
+  double* d_partial = nullptr;  // [kMaxPartials * 6]
+  double* d_diag = nullptr;     // [6]
+};

@@ -1,0 +1,963 @@
+// lesmi: LES residual and Runge-Kutta stepping on MI355X (gfx950), C ABI in include/lesmi.h.
+//
+// Method: Junqueira-Junior, Yamouni, Azevedo & Wolf, arXiv 2212.12365. Each kernel cites
+// the paper section whose equations it evaluates.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "les_common.h"
+
+using namespace lesmi;
+
+namespace {
+
+constexpr int kBlock = 256;
+constexpr int kMaxPartials = 4096;
+
+inline unsigned grid_for(long long n, int block = kBlock) {
+  return (unsigned)((n + block - 1) / block);
+}
+
+// ---------------------------------------------------------------------------------------
+// Grid metrics (paper, Transformation of Coordinates).
+// ---------------------------------------------------------------------------------------
+struct Shift {
+  double s[3][3];
+};
+
+struct MetricArgs {
+  const double* xyz;
+  Dims D;
+  Shift sh;
+};
+
+// Coordinate c at an index that may lie one node past either end of a periodic direction;
+// the period translation is added per wrap.
+__device__ double coord(const MetricArgs& A, int c, int i, int j, int k) {
+  int ix[3] = {i, j, k};
+  double add = 0.0;
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    int n = A.D.n[d];
+    if (ix[d] < 0) {
+      ix[d] += n;
+      add -= A.sh.s[d][c];
+    } else if (ix[d] >= n) {
+      ix[d] -= n;
+      add += A.sh.s[d][c];
+    }
+  }
+  return A.xyz[(long long)c * A.D.N + nid(A.D, ix[0], ix[1], ix[2])] + add;
+}
+
+// Index step along direction e.
+__device__ __forceinline__ void step_ix(int* ix, int e, int by) { ix[e] += by; }
+
+// Difference rule along e at index ix for a function value(ix): centred inside and across
+// periodic wraps, second-order one-sided at the ends of a non-periodic direction.
+template <class F>
+__device__ double diff_rule(const Dims& D, int e, const int* ix, F value) {
+  int m = ix[e], n = D.n[e];
+  int a[3] = {ix[0], ix[1], ix[2]}, b[3] = {ix[0], ix[1], ix[2]}, c[3] = {ix[0], ix[1], ix[2]};
+  if (D.per[e] || (m > 0 && m < n - 1)) {
+    step_ix(a, e, 1);
+    step_ix(b, e, -1);
+    return 0.5 * (value(a) - value(b));
+  }
+  if (m == 0) {
+    b[e] = 1;
+    c[e] = 2;
+    return 0.5 * (-3.0 * value(a) + 4.0 * value(b) - value(c));
+  }
+  b[e] = n - 2;
+  c[e] = n - 3;
+  return 0.5 * (3.0 * value(a) - 4.0 * value(b) + value(c));
+}
+
+__global__ void k_metrics(MetricArgs A, double* __restrict__ S, double* __restrict__ jinv) {
+  long long id = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (id >= A.D.N) return;
+  int i = (int)(id % A.D.n[0]);
+  int j = (int)((id / A.D.n[0]) % A.D.n[1]);
+  int k = (int)(id / ((long long)A.D.n[0] * A.D.n[1]));
+  int ix[3] = {i, j, k};
+  double r[3][3];  // r[e][c] = delta_e x_c
+  for (int e = 0; e < 3; ++e)
+    for (int c = 0; c < 3; ++c)
+      r[e][c] = diff_rule(A.D, e, ix, [&](const int* p) { return coord(A, c, p[0], p[1], p[2]); });
+  // J^-1 = det[r_xi, r_eta, r_zeta].
+  jinv[id] = r[0][0] * (r[1][1] * r[2][2] - r[2][1] * r[1][2]) -
+             r[1][0] * (r[0][1] * r[2][2] - r[2][1] * r[0][2]) +
+             r[2][0] * (r[0][1] * r[1][2] - r[1][1] * r[0][2]);
+  // Conservative metrics: S_d^c = delta_{d+2}(x_{c+2} delta_{d+1} x_{c+1})
+  //                             - delta_{d+1}(x_{c+2} delta_{d+2} x_{c+1}).
+  for (int d = 0; d < 3; ++d) {
+    int d1 = (d + 1) % 3, d2 = (d + 2) % 3;
+    for (int c = 0; c < 3; ++c) {
+      int c1 = (c + 1) % 3, c2 = (c + 2) % 3;
+      auto prod = [&](int inner) {
+        return [&, inner](const int* p) {
+          double dx = diff_rule(A.D, inner, p, [&](const int* q) {
+            return coord(A, c1, q[0], q[1], q[2]);
+          });
+          return coord(A, c2, p[0], p[1], p[2]) * dx;
+        };
+      };
+      double t1 = diff_rule(A.D, d2, ix, prod(d1));
+      double t2 = diff_rule(A.D, d1, ix, prod(d2));
+      S[(long long)(3 * d + c) * A.D.N + id] = t1 - t2;
+    }
+  }
+}
+
+// J = 1/J^-1 at updated nodes; flags J^-1 <= 0 there.
+__global__ void k_jacobian(Dims D, const double* __restrict__ jinv, double* __restrict__ jac,
+                           int* __restrict__ flag) {
+  long long id = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (id >= D.N) return;
+  int i = (int)(id % D.n[0]);
+  int j = (int)((id / D.n[0]) % D.n[1]);
+  int k = (int)(id / ((long long)D.n[0] * D.n[1]));
+  if (is_updated(D, i, j, k)) {
+    double v = jinv[id];
+    if (!(v > 0.0)) atomicOr(flag, 1);
+    jac[id] = 1.0 / v;
+  } else {
+    jac[id] = 0.0;
+  }
+}
+
+// Unit outward normals of the boundary faces from the metrics.
+__global__ void k_bc_normals(Dims D, const double* __restrict__ S, BcData B) {
+  int ni = D.n[0], nj = D.n[1], nk = D.n[2];
+  long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  long long nff = (long long)ni * nk, nfx = (long long)nj * nk;
+  auto unit = [&](int d, long long id, double sign, double* out, long long stride,
+                  long long o) {
+    double sx = S[(long long)(3 * d) * D.N + id], sy = S[(long long)(3 * d + 1) * D.N + id],
+           sz = S[(long long)(3 * d + 2) * D.N + id];
+    double m = sqrt(sx * sx + sy * sy + sz * sz);
+    out[o] = sign * sx / m;
+    out[stride + o] = sign * sy / m;
+    out[2 * stride + o] = sign * sz / m;
+  };
+  if (t < nff) {
+    int i = (int)(t % ni), k = (int)(t / ni);
+    unit(1, nid(D, i, nj - 1, k), 1.0, B.nff, nff, t);
+  } else if (t < nff + nfx) {
+    long long o = t - nff;
+    int j = (int)(o % nj), k = (int)(o / nj);
+    unit(0, nid(D, 0, j, k), -1.0, B.nin, nfx, o);
+    // The xi metric vanishes on the axis: the axis exit node takes the normal of j = 1.
+    unit(0, nid(D, ni - 1, j == 0 ? 1 : j, k), 1.0, B.nex, nfx, o);
+  }
+}
+
+// ---------------------------------------------------------------------------------------
+// Residual pipeline (paper, Spatial Discretization).
+// ---------------------------------------------------------------------------------------
+__global__ void k_prims(Dims D, Phys P, const double* __restrict__ q, double* __restrict__ pr) {
+  long long id = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (id >= D.N) return;
+  long long N = D.N;
+  Prim s = prim_from_q(q[id], q[N + id], q[2 * N + id], q[3 * N + id], q[4 * N + id], P);
+  pr[id] = s.rho;
+  pr[N + id] = s.u;
+  pr[2 * N + id] = s.v;
+  pr[3 * N + id] = s.w;
+  pr[4 * N + id] = s.p;
+  pr[5 * N + id] = s.T;
+  pr[6 * N + id] = sutherland(s.T, P);
+}
+
+// Difference of field f along e at (i,j,k): centred, periodic wrap, one-sided at the ends.
+__device__ __forceinline__ double dnode(const Dims& D, const double* f, int e, int i, int j,
+                                        int k) {
+  int ix[3] = {i, j, k};
+  int m = ix[e], n = D.n[e];
+  int a[3] = {i, j, k}, b[3] = {i, j, k}, c[3] = {i, j, k};
+  if (D.per[e]) {
+    a[e] = (m + 1 == n) ? 0 : m + 1;
+    b[e] = (m == 0) ? n - 1 : m - 1;
+    return 0.5 * (f[nid(D, a[0], a[1], a[2])] - f[nid(D, b[0], b[1], b[2])]);
+  }
+  if (m == 0) {
+    b[e] = 1;
+    c[e] = 2;
+    return 0.5 * (-3.0 * f[nid(D, a[0], a[1], a[2])] + 4.0 * f[nid(D, b[0], b[1], b[2])] -
+                  f[nid(D, c[0], c[1], c[2])]);
+  }
+  if (m == n - 1) {
+    b[e] = n - 2;
+    c[e] = n - 3;
+    return 0.5 * (3.0 * f[nid(D, a[0], a[1], a[2])] - 4.0 * f[nid(D, b[0], b[1], b[2])] +
+                  f[nid(D, c[0], c[1], c[2])]);
+  }
+  a[e] = m + 1;
+  b[e] = m - 1;
+  return 0.5 * (f[nid(D, a[0], a[1], a[2])] - f[nid(D, b[0], b[1], b[2])]);
+}
+
+// Node quantities: differences of (u, v, w, T), eddy viscosity, scaled spectral radii and
+// pressure sensors (paper, Subgrid Scale Viscosity; Spatial Discretization).
+// Layout of `node`: [e*4 + v] = delta_e var_v (12), [12] mu_t, [13..15] Lb_d, [16..18] nu_d.
+__global__ void k_node(Dims D, Phys P, const double* __restrict__ pr,
+                       const double* __restrict__ S, const double* __restrict__ jinv,
+                       double* __restrict__ node) {
+  long long id = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (id >= D.N) return;
+  long long N = D.N;
+  int i = (int)(id % D.n[0]);
+  int j = (int)((id / D.n[0]) % D.n[1]);
+  int k = (int)(id / ((long long)D.n[0] * D.n[1]));
+  double dq[3][3];
+  for (int e = 0; e < 3; ++e) {
+    for (int v = 0; v < 4; ++v) {
+      double val = dnode(D, pr + (1 + (v < 3 ? v : 4)) * N, e, i, j, k);
+      node[(long long)(e * 4 + v) * N + id] = val;
+      if (v < 3) dq[e][v] = val;
+    }
+  }
+  double s[9];
+  for (int c = 0; c < 9; ++c) s[c] = S[(long long)c * N + id];
+  double rho = pr[id], u = pr[N + id], v = pr[2 * N + id], w = pr[3 * N + id];
+  node[12 * N + id] = smagorinsky(s, dq, rho, jinv[id], P);
+  double a = sqrt(pr[5 * N + id]);
+  double l0 = spectral(s[0], s[1], s[2], u, v, w, a);
+  double l1 = spectral(s[3], s[4], s[5], u, v, w, a);
+  double l2 = spectral(s[6], s[7], s[8], u, v, w, a);
+  double lb[3];
+  scaled_radii(l0, l1, l2, lb);
+  node[13 * N + id] = lb[0];
+  node[14 * N + id] = lb[1];
+  node[15 * N + id] = lb[2];
+  const double* p = pr + 4 * N;
+  int ix[3] = {i, j, k};
+  for (int e = 0; e < 3; ++e) {
+    int c[3] = {i, j, k};
+    int n = D.n[e];
+    if (!D.per[e]) {  // boundary nodes take the sensor of the adjacent interior node
+      if (ix[e] == 0) c[e] = 1;
+      if (ix[e] == n - 1) c[e] = n - 2;
+    }
+    int a1[3] = {c[0], c[1], c[2]}, b1[3] = {c[0], c[1], c[2]};
+    a1[e] = (c[e] + 1 == n) ? 0 : c[e] + 1;
+    b1[e] = (c[e] == 0) ? n - 1 : c[e] - 1;
+    node[(long long)(16 + e) * N + id] =
+        sensor(p[nid(D, b1[0], b1[1], b1[2])], p[nid(D, c[0], c[1], c[2])],
+               p[nid(D, a1[0], a1[1], a1[2])]);
+  }
+}
+
+// Total numerical flux on the face between node A and its + neighbour along d:
+// H = (F_A + F_B)/2 - D - F_v (paper, Spatial Discretization, interface flux with the
+// Turkel-Vatsa terms; viscous flux from the two nodes of the interface).
+template <int d>
+__global__ void k_face(Dims D, Phys P, const double* __restrict__ q,
+                       const double* __restrict__ pr, const double* __restrict__ node,
+                       const double* __restrict__ S, const double* __restrict__ jinv,
+                       double* __restrict__ H) {
+  long long a = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (a >= D.N) return;
+  long long N = D.N;
+  int ix[3];
+  ix[0] = (int)(a % D.n[0]);
+  ix[1] = (int)((a / D.n[0]) % D.n[1]);
+  ix[2] = (int)(a / ((long long)D.n[0] * D.n[1]));
+  int n = D.n[d], m = ix[d];
+  if (!D.per[d] && m == n - 1) {
+    for (int c = 0; c < 5; ++c) H[(long long)c * N + a] = 0.0;
+    return;
+  }
+  auto at = [&](int off) {
+    int t[3] = {ix[0], ix[1], ix[2]};
+    int mm = m + off;
+    if (mm < 0) mm += n;
+    if (mm >= n) mm -= n;
+    t[d] = mm;
+    return nid(D, t[0], t[1], t[2]);
+  };
+  long long b = at(1);
+  // Inviscid node fluxes.
+  double qa[5], qbv[5], FA[5], FB[5];
+  for (int c = 0; c < 5; ++c) {
+    qa[c] = q[(long long)c * N + a];
+    qbv[c] = q[(long long)c * N + b];
+  }
+  Prim sa{pr[a], pr[N + a], pr[2 * N + a], pr[3 * N + a], pr[4 * N + a], pr[5 * N + a]};
+  Prim sb{pr[b], pr[N + b], pr[2 * N + b], pr[3 * N + b], pr[4 * N + b], pr[5 * N + b]};
+  inviscid_flux(S[(3 * d) * N + a], S[(3 * d + 1) * N + a], S[(3 * d + 2) * N + a], qa, sa, FA);
+  inviscid_flux(S[(3 * d) * N + b], S[(3 * d + 1) * N + b], S[(3 * d + 2) * N + b], qbv, sb,
+                FB);
+  // Dissipated vector W = Q + (0,0,0,0,p) and its differences; at the first and last face of
+  // a non-periodic direction (Delta W)_outside = -(Delta W)_inside.
+  auto Wv = [&](long long id, int c) {
+    double v = q[(long long)c * N + id];
+    if (c == 4) v += pr[4 * N + id];
+    return v;
+  };
+  double dW[5], d3W[5];
+  if (D.per[d] || (m > 0 && m < n - 2)) {
+    long long am = at(-1), bp = at(2);
+    for (int c = 0; c < 5; ++c) {
+      double wA = Wv(a, c), wB = Wv(b, c);
+      dW[c] = wB - wA;
+      d3W[c] = Wv(bp, c) - 3.0 * wB + 3.0 * wA - Wv(am, c);
+    }
+  } else if (m == 0) {
+    long long bp = at(2);
+    for (int c = 0; c < 5; ++c) {
+      double wA = Wv(a, c), wB = Wv(b, c);
+      dW[c] = wB - wA;
+      d3W[c] = (Wv(bp, c) - wB) - 3.0 * dW[c];
+    }
+  } else {  // m == n - 2
+    long long am = at(-1);
+    for (int c = 0; c < 5; ++c) {
+      double wA = Wv(a, c), wB = Wv(b, c);
+      dW[c] = wB - wA;
+      d3W[c] = -3.0 * dW[c] + (wA - Wv(am, c));
+    }
+  }
+  double lf = 0.5 * (node[(13 + d) * N + a] + node[(13 + d) * N + b]);
+  double Dd[5];
+  dissipation(lf, node[(16 + d) * N + a], node[(16 + d) * N + b], dW, d3W, P, Dd);
+  // Viscous flux: compact difference along d, averaged nodal differences across.
+  double Sf[9];
+  for (int c = 0; c < 9; ++c) Sf[c] = 0.5 * (S[(long long)c * N + a] + S[(long long)c * N + b]);
+  double jf = 0.5 * (jinv[a] + jinv[b]);
+  double gxi[4][3];
+  const int var_slot[4] = {1, 2, 3, 5};
+  for (int v = 0; v < 4; ++v)
+    for (int e = 0; e < 3; ++e) {
+      if (e == d)
+        gxi[v][e] = pr[var_slot[v] * N + b] - pr[var_slot[v] * N + a];
+      else
+        gxi[v][e] = 0.5 * (node[(long long)(e * 4 + v) * N + a] + node[(long long)(e * 4 + v) * N + b]);
+    }
+  double muf = 0.5 * (pr[6 * N + a] + pr[6 * N + b]);
+  double mutf = 0.5 * (node[12 * N + a] + node[12 * N + b]);
+  double ub[3] = {0.5 * (sa.u + sb.u), 0.5 * (sa.v + sb.v), 0.5 * (sa.w + sb.w)};
+  double Fv[5];
+  viscous_flux(Sf, jf, gxi, muf, mutf, ub, d, P, Fv);
+  Fv[0] = 0.0;
+  for (int c = 0; c < 5; ++c) H[(long long)c * N + a] = 0.5 * (FA[c] + FB[c]) - Dd[c] - Fv[c];
+}
+
+// RHS = sum_d (H_{+1/2} - H_{-1/2}) at updated nodes. Mode 0 writes rhs; mode 1 writes the
+// Runge-Kutta stage Q^(l) = Q^(0) - alpha dt J RHS (paper, Time Marching Method).
+__global__ void k_rhs(Dims D, const double* __restrict__ H, double* __restrict__ out,
+                      const double* __restrict__ q0, const double* __restrict__ jac,
+                      const double* __restrict__ dtp, double alpha, int mode) {
+  long long id = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (id >= D.N) return;
+  long long N = D.N;
+  int ix[3];
+  ix[0] = (int)(id % D.n[0]);
+  ix[1] = (int)((id / D.n[0]) % D.n[1]);
+  ix[2] = (int)(id / ((long long)D.n[0] * D.n[1]));
+  bool upd = is_updated(D, ix[0], ix[1], ix[2]);
+  if (!upd) {
+    if (mode == 0)
+      for (int c = 0; c < 5; ++c) out[(long long)c * N + id] = 0.0;
+    return;
+  }
+  long long prev[3];
+  for (int d = 0; d < 3; ++d) {
+    int t[3] = {ix[0], ix[1], ix[2]};
+    t[d] = (ix[d] == 0) ? D.n[d] - 1 : ix[d] - 1;
+    prev[d] = nid(D, t[0], t[1], t[2]);
+  }
+  double fac = 0.0;
+  if (mode == 1) fac = alpha * dtp[0] * jac[id];
+  for (int c = 0; c < 5; ++c) {
+    const double* Hc = H + (long long)c * N;
+    double r = 0.0;
+    for (int d = 0; d < 3; ++d) r += Hc[(long long)d * 5 * N + id] - Hc[(long long)d * 5 * N + prev[d]];
+    if (mode == 0)
+      out[(long long)c * N + id] = r;
+    else
+      out[(long long)c * N + id] = q0[(long long)c * N + id] - fac * r;
+  }
+}
+
+// ---------------------------------------------------------------------------------------
+// Boundary conditions (paper, Boundary Conditions).
+// ---------------------------------------------------------------------------------------
+
+// Far-field Riemann state from the interior state qe and the unit outward normal n.
+__device__ void farfield_state(const Phys& P, const BcData& B, const double* qe,
+                               const double* n, double* qo) {
+  double g = P.gamma;
+  double re = qe[0];
+  double ue[3] = {qe[1] / re, qe[2] / re, qe[3] / re};
+  double pe = P.gm1 * (qe[4] - 0.5 * re * (ue[0] * ue[0] + ue[1] * ue[1] + ue[2] * ue[2]));
+  double ae = sqrt(g * pe / re);
+  double ainf = sqrt(g * B.p_inf / B.rho_inf);
+  double qne = ue[0] * n[0] + ue[1] * n[1] + ue[2] * n[2];
+  double qninf = B.u_inf[0] * n[0] + B.u_inf[1] * n[1] + B.u_inf[2] * n[2];
+  double rp = qne + 2.0 * ae * P.inv_gm1;
+  double rm = qninf - 2.0 * ainf * P.inv_gm1;
+  double qnf = 0.5 * (rp + rm);
+  double af = 0.25 * P.gm1 * (rp - rm);
+  double mn = qne / ae;
+  double uf[3], rf, pf;
+  if (mn >= 1.0) {
+    for (int c = 0; c < 5; ++c) qo[c] = qe[c];
+    return;
+  } else if (mn >= 0.0) {
+    for (int c = 0; c < 3; ++c) uf[c] = ue[c] + (qnf - qne) * n[c];
+    rf = pow(pow(re, g) * af * af / (g * pe), P.inv_gm1);
+    pf = rf * af * af / g;
+  } else if (mn > -1.0) {
+    for (int c = 0; c < 3; ++c) uf[c] = B.u_inf[c] + (qnf - qninf) * n[c];
+    rf = pow(pow(B.rho_inf, g) * af * af / (g * B.p_inf), P.inv_gm1);
+    pf = rf * af * af / g;
+  } else {
+    for (int c = 0; c < 3; ++c) uf[c] = B.u_inf[c];
+    rf = B.rho_inf;
+    pf = B.p_inf;
+  }
+  qo[0] = rf;
+  qo[1] = rf * uf[0];
+  qo[2] = rf * uf[1];
+  qo[3] = rf * uf[2];
+  qo[4] = pf * P.inv_gm1 + 0.5 * rf * (uf[0] * uf[0] + uf[1] * uf[1] + uf[2] * uf[2]);
+}
+
+// Centreline means of the first ring, summed in k order (paper, Centerline Boundary
+// Condition).
+__global__ void k_axis_mean(Dims D, const double* __restrict__ q, double* __restrict__ axis) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < 1 || i > D.n[0] - 2) return;
+  long long N = D.N;
+  for (int c = 0; c < 5; ++c) {
+    double s = 0.0;
+    for (int k = 0; k < D.n[2]; ++k) s += q[(long long)c * N + nid(D, i, 1, k)];
+    axis[(long long)c * D.n[0] + i] = s / (double)D.n[2];
+  }
+}
+
+__device__ __forceinline__ void load_q(const double* q, long long N, long long id, double* o) {
+  for (int c = 0; c < 5; ++c) o[c] = q[(long long)c * N + id];
+}
+
+// One thread per boundary node. Far field (j = nj-1, 1 <= i <= ni-2), centreline (j = 0,
+// 1 <= i <= ni-2), entrance (i = 0), exit (i = ni-1). Each boundary value is composed from
+// updated nodes only, reproducing the order far field -> centreline -> entrance -> exit.
+__global__ void k_bc(Dims D, Phys P, BcData B, double* __restrict__ q) {
+  int ni = D.n[0], nj = D.n[1], nk = D.n[2];
+  long long N = D.N;
+  long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  long long nrow = (long long)(ni - 2) * nk;
+  long long nface = (long long)nj * nk;
+  double qe[5], qo[5], n[3];
+  auto ff_normal = [&](int i, int k, double* o) {
+    long long s = (long long)ni * nk, off = i + (long long)ni * k;
+    o[0] = B.nff[off];
+    o[1] = B.nff[s + off];
+    o[2] = B.nff[2 * s + off];
+  };
+  // Far-field state of node (i, nj-1, k), from its interior neighbour.
+  auto farfield_node = [&](int i, int k, double* o) {
+    double qi[5], nn[3];
+    load_q(q, N, nid(D, i, nj - 2, k), qi);
+    ff_normal(i, k, nn);
+    farfield_state(P, B, qi, nn, o);
+  };
+  // State of node (i, j, k) after the far field and centreline conditions.
+  auto after_j = [&](int i, int j, int k, double* o) {
+    if (j == nj - 1)
+      farfield_node(i, k, o);
+    else if (j == 0)
+      for (int c = 0; c < 5; ++c) o[c] = B.axis[(long long)c * ni + i];
+    else
+      load_q(q, N, nid(D, i, j, k), o);
+  };
+  long long id;
+  if (t < nrow) {  // far field
+    int i = 1 + (int)(t % (ni - 2)), k = (int)(t / (ni - 2));
+    farfield_node(i, k, qo);
+    id = nid(D, i, nj - 1, k);
+  } else if (t < 2 * nrow) {  // centreline
+    long long o = t - nrow;
+    int i = 1 + (int)(o % (ni - 2)), k = (int)(o / (ni - 2));
+    for (int c = 0; c < 5; ++c) qo[c] = B.axis[(long long)c * ni + i];
+    id = nid(D, i, 0, k);
+  } else if (t < 2 * nrow + nface) {  // entrance
+    long long o = t - 2 * nrow;
+    int j = (int)(o % nj), k = (int)(o / nj);
+    id = nid(D, 0, j, k);
+    if (B.jetmask[o]) {
+      double uj = B.mach_jet;
+      qo[0] = 1.0;
+      qo[1] = uj;
+      qo[2] = 0.0;
+      qo[3] = 0.0;
+      qo[4] = (1.0 / P.gamma) * P.inv_gm1 + 0.5 * uj * uj;
+    } else {
+      after_j(1, j, k, qe);
+      n[0] = B.nin[o];
+      n[1] = B.nin[nface + o];
+      n[2] = B.nin[2 * nface + o];
+      farfield_state(P, B, qe, n, qo);
+    }
+  } else if (t < 2 * nrow + 2 * nface) {  // exit
+    long long o = t - 2 * nrow - nface;
+    int j = (int)(o % nj), k = (int)(o / nj);
+    id = nid(D, ni - 1, j, k);
+    after_j(ni - 2, j, k, qe);
+    n[0] = B.nex[o];
+    n[1] = B.nex[nface + o];
+    n[2] = B.nex[2 * nface + o];
+    double re = qe[0];
+    double ue[3] = {qe[1] / re, qe[2] / re, qe[3] / re};
+    double pe = P.gm1 * (qe[4] - 0.5 * re * (ue[0] * ue[0] + ue[1] * ue[1] + ue[2] * ue[2]));
+    double ae = sqrt(P.gamma * pe / re);
+    double mn = (ue[0] * n[0] + ue[1] * n[1] + ue[2] * n[2]) / ae;
+    if (mn >= 1.0) {
+      for (int c = 0; c < 5; ++c) qo[c] = qe[c];
+    } else {
+      double eint = pe / (P.gm1 * re);
+      double rb = B.p_inf / (P.gm1 * eint);
+      qo[0] = rb;
+      qo[1] = rb * ue[0];
+      qo[2] = rb * ue[1];
+      qo[3] = rb * ue[2];
+      qo[4] = B.p_inf * P.inv_gm1 + 0.5 * rb * (ue[0] * ue[0] + ue[1] * ue[1] + ue[2] * ue[2]);
+    }
+  } else {
+    return;
+  }
+  for (int c = 0; c < 5; ++c) q[(long long)c * N + id] = qo[c];
+}
+
+// ---------------------------------------------------------------------------------------
+// Time step: dt = CFL min over updated nodes of J^-1 / sum_d Lam_d. A positive double's
+// bit pattern orders like the value, so the minimum is an exact integer atomic minimum.
+// ---------------------------------------------------------------------------------------
+__global__ void k_dt_reset(unsigned long long* bits) { bits[0] = 0x7ff0000000000000ull; }
+
+__global__ void k_dt_partial(Dims D, Phys P, const double* __restrict__ q,
+                             const double* __restrict__ S, const double* __restrict__ jinv,
+                             unsigned long long* __restrict__ bits, int* __restrict__ flag) {
+  __shared__ double red[kBlock];
+  long long id = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  double r = INFINITY;
+  if (id < D.N) {
+    int i = (int)(id % D.n[0]);
+    int j = (int)((id / D.n[0]) % D.n[1]);
+    int k = (int)(id / ((long long)D.n[0] * D.n[1]));
+    if (is_updated(D, i, j, k)) {
+      long long N = D.N;
+      Prim s = prim_from_q(q[id], q[N + id], q[2 * N + id], q[3 * N + id], q[4 * N + id], P);
+      double a = sqrt(s.T);
+      double l = spectral(S[id], S[N + id], S[2 * N + id], s.u, s.v, s.w, a) +
+                 spectral(S[3 * N + id], S[4 * N + id], S[5 * N + id], s.u, s.v, s.w, a) +
+                 spectral(S[6 * N + id], S[7 * N + id], S[8 * N + id], s.u, s.v, s.w, a);
+      r = jinv[id] / l;
+      if (!(s.rho > 0.0) || !(s.p > 0.0) || !isfinite(r)) atomicOr(flag, 2);
+    }
+  }
+  red[threadIdx.x] = r;
+  __syncthreads();
+  for (int o = kBlock / 2; o > 0; o >>= 1) {
+    if ((int)threadIdx.x < o) red[threadIdx.x] = fmin(red[threadIdx.x], red[threadIdx.x + o]);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0 && red[0] < INFINITY) {
+    atomicMin(bits, (unsigned long long)__double_as_longlong(red[0]));
+  }
+}
+
+__global__ void k_dt_final(const unsigned long long* __restrict__ bits, double cfl,
+                           double* __restrict__ dt) {
+  dt[0] = cfl * __longlong_as_double((long long)bits[0]);
+}
+
+__global__ void k_set_scalar(double* p, double v) { p[0] = v; }
+__global__ void k_set_int(int* p, int v) { p[0] = v; }
+
+// Non-finite or non-positive density/pressure anywhere in q sets flag bit 2.
+__global__ void k_check(Dims D, Phys P, const double* __restrict__ q, int* __restrict__ flag) {
+  long long id = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (id >= D.N) return;
+  long long N = D.N;
+  Prim s = prim_from_q(q[id], q[N + id], q[2 * N + id], q[3 * N + id], q[4 * N + id], P);
+  bool ok = s.rho > 0.0 && s.p > 0.0 && isfinite(s.u) && isfinite(s.v) && isfinite(s.w) &&
+            isfinite(q[4 * N + id]);
+  if (!ok) atomicOr(flag, 2);
+}
+
+// ---------------------------------------------------------------------------------------
+// Diagnostics: per-block partial sums over fixed node ranges, then one fixed-order pass.
+// ---------------------------------------------------------------------------------------
+__global__ void k_diag_partial(Dims D, const double* __restrict__ q,
+                               const double* __restrict__ jinv, double* __restrict__ part,
+                               long long chunk) {
+  __shared__ double red[6][kBlock];
+  long long N = D.N;
+  long long lo = (long long)blockIdx.x * chunk, hi = lo + chunk < N ? lo + chunk : N;
+  double acc[6] = {0, 0, 0, 0, 0, 0};  // vol, ke, then... packed below
+  double tot[5] = {0, 0, 0, 0, 0};
+  double vol = 0.0, ke = 0.0;
+  for (long long id = lo + threadIdx.x; id < hi; id += blockDim.x) {
+    int i = (int)(id % D.n[0]);
+    int j = (int)((id / D.n[0]) % D.n[1]);
+    int k = (int)(id / ((long long)D.n[0] * D.n[1]));
+    if (!is_updated(D, i, j, k)) continue;
+    double w = jinv[id];
+    double r = q[id];
+    double m2 = q[N + id] * q[N + id] + q[2 * N + id] * q[2 * N + id] + q[3 * N + id] * q[3 * N + id];
+    vol += w;
+    ke += w * 0.5 * m2 / r;
+    for (int c = 0; c < 5; ++c) tot[c] += w * q[(long long)c * N + id];
+  }
+  (void)acc;
+  // Slot 0 = ke, slots 1..5 = totals; the volume goes to a separate partial row.
+  red[0][threadIdx.x] = ke;
+  for (int c = 0; c < 5; ++c) red[1 + c][threadIdx.x] = tot[c];
+  __syncthreads();
+  for (int o = kBlock / 2; o > 0; o >>= 1) {
+    if ((int)threadIdx.x < o)
+      for (int s = 0; s < 6; ++s) red[s][threadIdx.x] += red[s][threadIdx.x + o];
+    __syncthreads();
+  }
+  if (threadIdx.x < 6) part[(long long)blockIdx.x * 7 + threadIdx.x] = red[threadIdx.x][0];
+  __syncthreads();
+  red[0][threadIdx.x] = vol;
+  __syncthreads();
+  for (int o = kBlock / 2; o > 0; o >>= 1) {
+    if ((int)threadIdx.x < o) red[0][threadIdx.x] += red[0][threadIdx.x + o];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) part[(long long)blockIdx.x * 7 + 6] = red[0][0];
+}
+
+__global__ void k_diag_final(const double* __restrict__ part, int nparts,
+                             double* __restrict__ out) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  double s[7] = {0, 0, 0, 0, 0, 0, 0};
+  for (int b = 0; b < nparts; ++b)
+    for (int c = 0; c < 7; ++c) s[c] += part[(long long)b * 7 + c];
+  out[0] = s[0] / s[6];
+  for (int c = 0; c < 5; ++c) out[1 + c] = s[1 + c];
+}
+
+__global__ void k_copy(long long n, const double* __restrict__ src, double* __restrict__ dst) {
+  long long id = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (id < n) dst[id] = src[id];
+}
+
+// ---------------------------------------------------------------------------------------
+// Host side.
+// ---------------------------------------------------------------------------------------
+int fail(les_ctx* c, int code, const char* msg) {
+  if (c) c->err = msg;
+  return code;
+}
+
+#define HIP_TRY(ctx, expr)                                                             \
+  do {                                                                                 \
+    hipError_t e_ = (expr);                                                            \
+    if (e_ != hipSuccess) {                                                            \
+      if (ctx) {                                                                       \
+        (ctx)->err = std::string(#expr) + ": " + hipGetErrorString(e_);                \
+      }                                                                                \
+      return LES_EHIP;                                                                 \
+    }                                                                                  \
+  } while (0)
+
+int launch_check(les_ctx* c, const char* what) {
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) {
+    c->err = std::string(what) + ": " + hipGetErrorString(e);
+    return LES_EHIP;
+  }
+  return LES_OK;
+}
+
+int validate(const les_params* p, Dims* D) {
+  if (!p) return LES_EINVAL;
+  int n[3] = {p->ni, p->nj, p->nk};
+  for (int d = 0; d < 3; ++d) {
+    if (n[d] < 4) return LES_EINVAL;
+    int lo = p->bc[2 * d], hi = p->bc[2 * d + 1];
+    if ((lo == LES_BC_PERIODIC) != (hi == LES_BC_PERIODIC)) return LES_EINVAL;
+    D->n[d] = n[d];
+    D->per[d] = lo == LES_BC_PERIODIC;
+  }
+  bool box = D->per[0] && D->per[1] && D->per[2];
+  bool jet = p->bc[0] == LES_BC_JET_INFLOW && p->bc[1] == LES_BC_EXIT && p->bc[2] == LES_BC_AXIS &&
+             p->bc[3] == LES_BC_FARFIELD && D->per[2];
+  if (!box && !jet) return LES_EINVAL;
+  if (!(p->gamma > 1.0) || p->re_acoustic < 0.0 || !(p->prandtl > 0.0) ||
+      !(p->prandtl_sgs > 0.0))
+    return LES_EINVAL;
+  if (p->precision != LES_FP64) return LES_EINVAL;
+  if (p->closure != LES_SMAGORINSKY) return LES_EINVAL;
+  D->jet = jet ? 1 : 0;
+  D->N = (long long)n[0] * n[1] * n[2];
+  return LES_OK;
+}
+
+Phys make_phys(const les_params& p) {
+  Phys P;
+  P.gamma = p.gamma;
+  P.gm1 = p.gamma - 1.0;
+  P.inv_gm1 = 1.0 / (p.gamma - 1.0);
+  P.inv_re = p.re_acoustic > 0.0 ? 1.0 / p.re_acoustic : 0.0;
+  P.inv_pr = 1.0 / p.prandtl;
+  P.inv_prs = 1.0 / p.prandtl_sgs;
+  P.s1 = p.suth_s1;
+  P.s1p1 = 1.0 + p.suth_s1;
+  P.cs2 = p.cs * p.cs;
+  P.k2 = p.k2;
+  P.k4 = p.k4;
+  return P;
+}
+
+template <class T>
+int dev_alloc(les_ctx* c, T** p, size_t count) {
+  hipError_t e = hipMalloc((void**)p, count * sizeof(T));
+  if (e != hipSuccess) {
+    *p = nullptr;
+    c->err = std::string("hipMalloc: ") + hipGetErrorString(e);
+    return LES_ENOMEM;
+  }
+  return LES_OK;
+}
+
+void free_ctx(les_ctx* c) {
+  if (!c) return;
+  void* ptrs[] = {c->S, c->jinv, c->jac, c->bc.nff, c->bc.nin, c->bc.nex, c->bc.jetmask,
+                  c->bc.axis, c->qa, c->qb, c->prim, c->node, c->flux, c->rhs, c->d_dt,
+                  c->d_minbits, c->d_flag, c->d_partial, c->d_diag};
+  for (void* p : ptrs)
+    if (p) (void)hipFree(p);
+}
+
+// Residual pipeline on q into the face-flux buffer.
+int run_fluxes(les_ctx* c, const double* q, hipStream_t s) {
+  const Dims& D = c->dims;
+  unsigned g = grid_for(D.N);
+  hipLaunchKernelGGL(k_prims, dim3(g), dim3(kBlock), 0, s, D, c->phys, q, c->prim);
+  hipLaunchKernelGGL(k_node, dim3(g), dim3(kBlock), 0, s, D, c->phys, c->prim, c->S, c->jinv,
+                     c->node);
+  hipLaunchKernelGGL(k_face<0>, dim3(g), dim3(kBlock), 0, s, D, c->phys, q, c->prim, c->node,
+                     c->S, c->jinv, c->flux);
+  hipLaunchKernelGGL(k_face<1>, dim3(g), dim3(kBlock), 0, s, D, c->phys, q, c->prim, c->node,
+                     c->S, c->jinv, c->flux + 5 * D.N);
+  hipLaunchKernelGGL(k_face<2>, dim3(g), dim3(kBlock), 0, s, D, c->phys, q, c->prim, c->node,
+                     c->S, c->jinv, c->flux + 10 * D.N);
+  return launch_check(c, "residual kernels");
+}
+
+int run_bc(les_ctx* c, double* q, hipStream_t s) {
+  const Dims& D = c->dims;
+  if (!D.jet) return LES_OK;
+  hipLaunchKernelGGL(k_axis_mean, dim3(grid_for(D.n[0])), dim3(kBlock), 0, s, D, q, c->bc.axis);
+  long long nbc = 2LL * (D.n[0] - 2) * D.n[2] + 2LL * D.n[1] * D.n[2];
+  hipLaunchKernelGGL(k_bc, dim3(grid_for(nbc)), dim3(kBlock), 0, s, D, c->phys, c->bc, q);
+  return launch_check(c, "boundary kernels");
+}
+
+}  // namespace
+
+extern "C" {
+
+int les_init_grid(const les_params* params, const double* xyz, les_ctx** out) {
+  if (!out) return LES_EINVAL;
+  *out = nullptr;
+  Dims D{};
+  if (!params || !xyz) return LES_EINVAL;
+  int rc = validate(params, &D);
+  if (rc) return rc;
+  les_ctx* c = new (std::nothrow) les_ctx();
+  if (!c) return LES_ENOMEM;
+  c->params = *params;
+  c->dims = D;
+  c->phys = make_phys(*params);
+  c->n_updated = 1;
+  for (int d = 0; d < 3; ++d) c->n_updated *= D.per[d] ? D.n[d] : D.n[d] - 2;
+  hipGetDevice(&c->device);
+  long long N = D.N;
+  int ni = D.n[0], nj = D.n[1], nk = D.n[2];
+  double* d_xyz = nullptr;
+  auto bail = [&](int code) {
+    if (d_xyz) (void)hipFree(d_xyz);
+    free_ctx(c);
+    delete c;
+    return code;
+  };
+  if (dev_alloc(c, &c->S, 9 * N) || dev_alloc(c, &c->jinv, N) || dev_alloc(c, &c->jac, N) ||
+      dev_alloc(c, &c->qa, 5 * N) || dev_alloc(c, &c->qb, 5 * N) ||
+      dev_alloc(c, &c->prim, 7 * N) || dev_alloc(c, &c->node, 19 * N) ||
+      dev_alloc(c, &c->flux, 15 * N) || dev_alloc(c, &c->rhs, 5 * N) ||
+      dev_alloc(c, &c->d_dt, 1) || dev_alloc(c, &c->d_minbits, 1) ||
+      dev_alloc(c, &c->d_flag, 1) || dev_alloc(c, &c->d_partial, 7 * kMaxPartials) ||
+      dev_alloc(c, &c->d_diag, 8) || dev_alloc(c, &c->bc.nff, 3LL * ni * nk) ||
+      dev_alloc(c, &c->bc.nin, 3LL * nj * nk) || dev_alloc(c, &c->bc.nex, 3LL * nj * nk) ||
+      dev_alloc(c, &c->bc.jetmask, (long long)nj * nk) || dev_alloc(c, &c->bc.axis, 5LL * ni) ||
+      dev_alloc(c, &d_xyz, 3 * N))
+    return bail(LES_ENOMEM);
+  c->bc.rho_inf = params->rho_inf;
+  for (int d = 0; d < 3; ++d) c->bc.u_inf[d] = params->u_inf[d];
+  c->bc.p_inf = params->p_inf;
+  c->bc.mach_jet = params->mach_jet;
+  if (hipMemcpy(d_xyz, xyz, sizeof(double) * 3 * N, hipMemcpyHostToDevice) != hipSuccess)
+    return bail(LES_EHIP);
+  // Entrance nodes inside the jet radius.
+  std::vector<int> mask((size_t)nj * nk, 0);
+  if (D.jet)
+    for (int k = 0; k < nk; ++k)
+      for (int j = 0; j < nj; ++j) {
+        long long id = nid(D, 0, j, k);
+        double y = xyz[N + id], z = xyz[2 * N + id];
+        mask[(size_t)j + (size_t)nj * k] = std::sqrt(y * y + z * z) <= params->jet_radius;
+      }
+  if (hipMemcpy(c->bc.jetmask, mask.data(), sizeof(int) * mask.size(), hipMemcpyHostToDevice) !=
+      hipSuccess)
+    return bail(LES_EHIP);
+  MetricArgs A;
+  A.xyz = d_xyz;
+  A.D = D;
+  for (int d = 0; d < 3; ++d)
+    for (int e = 0; e < 3; ++e) A.sh.s[d][e] = params->period_shift[d][e];
+  hipLaunchKernelGGL(k_metrics, dim3(grid_for(N)), dim3(kBlock), 0, 0, A, c->S, c->jinv);
+  hipLaunchKernelGGL(k_set_int, dim3(1), dim3(1), 0, 0, c->d_flag, 0);
+  hipLaunchKernelGGL(k_jacobian, dim3(grid_for(N)), dim3(kBlock), 0, 0, D, c->jinv, c->jac,
+                     c->d_flag);
+  if (D.jet) {
+    long long nn = (long long)ni * nk + (long long)nj * nk;
+    hipLaunchKernelGGL(k_bc_normals, dim3(grid_for(nn)), dim3(kBlock), 0, 0, D, c->S, c->bc);
+  }
+  if (launch_check(c, "init kernels")) return bail(LES_EHIP);
+  int flag = 0;
+  if (hipMemcpy(&flag, c->d_flag, sizeof(int), hipMemcpyDeviceToHost) != hipSuccess)
+    return bail(LES_EHIP);
+  (void)hipFree(d_xyz);
+  d_xyz = nullptr;
+  *out = c;
+  if (flag) {
+    c->err = "J^-1 <= 0 at an updated node";
+    return LES_EGRID;
+  }
+  return LES_OK;
+}
+
+int les_residual(les_ctx* c, const double* q, double* rhs, void* stream) {
+  if (!c || !q || !rhs) return fail(c, LES_EINVAL, "null argument");
+  hipStream_t s = (hipStream_t)stream;
+  int rc = run_fluxes(c, q, s);
+  if (rc) return rc;
+  hipLaunchKernelGGL(k_rhs, dim3(grid_for(c->dims.N)), dim3(kBlock), 0, s, c->dims, c->flux,
+                     rhs, (const double*)nullptr, (const double*)nullptr, (const double*)nullptr,
+                     0.0, 0);
+  return launch_check(c, "k_rhs");
+}
+
+int les_sgs_viscosity(les_ctx* c, const double* q, double* mu_t, void* stream) {
+  if (!c || !q || !mu_t) return fail(c, LES_EINVAL, "null argument");
+  hipStream_t s = (hipStream_t)stream;
+  const Dims& D = c->dims;
+  unsigned g = grid_for(D.N);
+  hipLaunchKernelGGL(k_prims, dim3(g), dim3(kBlock), 0, s, D, c->phys, q, c->prim);
+  hipLaunchKernelGGL(k_node, dim3(g), dim3(kBlock), 0, s, D, c->phys, c->prim, c->S, c->jinv,
+                     c->node);
+  hipLaunchKernelGGL(k_copy, dim3(g), dim3(kBlock), 0, s, D.N, c->node + 12 * D.N, mu_t);
+  return launch_check(c, "sgs kernels");
+}
+
+int les_apply_bc(les_ctx* c, double* q, void* stream) {
+  if (!c || !q) return fail(c, LES_EINVAL, "null argument");
+  return run_bc(c, q, (hipStream_t)stream);
+}
+
+int les_step(les_ctx* c, double* q, int nsteps, double cfl, double dt_fixed, double* dt_last,
+             void* stream) {
+  if (!c || !q || nsteps < 0) return fail(c, LES_EINVAL, "bad argument");
+  if (!(cfl > 0.0) && !(dt_fixed > 0.0)) return fail(c, LES_EINVAL, "need cfl > 0 or dt_fixed > 0");
+  static const double alpha[5] = {0.25, 1.0 / 6.0, 0.375, 0.5, 1.0};
+  hipStream_t s = (hipStream_t)stream;
+  const Dims& D = c->dims;
+  unsigned g = grid_for(D.N);
+  hipLaunchKernelGGL(k_set_int, dim3(1), dim3(1), 0, s, c->d_flag, 0);
+  for (int n = 0; n < nsteps; ++n) {
+    if (cfl > 0.0) {
+      hipLaunchKernelGGL(k_dt_reset, dim3(1), dim3(1), 0, s, c->d_minbits);
+      hipLaunchKernelGGL(k_dt_partial, dim3(g), dim3(kBlock), 0, s, D, c->phys, q, c->S,
+                         c->jinv, c->d_minbits, c->d_flag);
+      hipLaunchKernelGGL(k_dt_final, dim3(1), dim3(1), 0, s, c->d_minbits, cfl, c->d_dt);
+    } else {
+      hipLaunchKernelGGL(k_set_scalar, dim3(1), dim3(1), 0, s, c->d_dt, dt_fixed);
+    }
+    const double* in = q;
+    for (int l = 0; l < 5; ++l) {
+      double* outb = (l == 4) ? q : ((l % 2 == 0) ? c->qa : c->qb);
+      int rc = run_fluxes(c, in, s);
+      if (rc) return rc;
+      hipLaunchKernelGGL(k_rhs, dim3(g), dim3(kBlock), 0, s, D, c->flux, outb, q, c->jac,
+                         c->d_dt, alpha[l], 1);
+      rc = run_bc(c, outb, s);
+      if (rc) return rc;
+      in = outb;
+    }
+  }
+  hipLaunchKernelGGL(k_check, dim3(g), dim3(kBlock), 0, s, D, c->phys, q, c->d_flag);
+  int rc = launch_check(c, "step kernels");
+  if (rc) return rc;
+  int flag = 0;
+  double dt = 0.0;
+  HIP_TRY(c, hipMemcpyAsync(&flag, c->d_flag, sizeof(int), hipMemcpyDeviceToHost, s));
+  HIP_TRY(c, hipMemcpyAsync(&dt, c->d_dt, sizeof(double), hipMemcpyDeviceToHost, s));
+  HIP_TRY(c, hipStreamSynchronize(s));
+  if (dt_last) *dt_last = dt;
+  if (flag) return fail(c, LES_ENONFINITE, "non-finite value or non-positive density/pressure");
+  return LES_OK;
+}
+
+int les_diagnostics(les_ctx* c, const double* q, double* out, void* stream) {
+  if (!c || !q || !out) return fail(c, LES_EINVAL, "null argument");
+  hipStream_t s = (hipStream_t)stream;
+  const Dims& D = c->dims;
+  long long chunk = (D.N + kMaxPartials - 1) / kMaxPartials;
+  if (chunk < 1024) chunk = 1024;
+  int nparts = (int)((D.N + chunk - 1) / chunk);
+  hipLaunchKernelGGL(k_diag_partial, dim3(nparts), dim3(kBlock), 0, s, D, q, c->jinv,
+                     c->d_partial, chunk);
+  hipLaunchKernelGGL(k_diag_final, dim3(1), dim3(1), 0, s, c->d_partial, nparts, c->d_diag);
+  int rc = launch_check(c, "diagnostics");
+  if (rc) return rc;
+  HIP_TRY(c, hipMemcpyAsync(out, c->d_diag, 6 * sizeof(double), hipMemcpyDeviceToHost, s));
+  HIP_TRY(c, hipStreamSynchronize(s));
+  return LES_OK;
+}
+
+int les_get_metrics(les_ctx* c, double* S, double* jinv, void* stream) {
+  if (!c) return LES_EINVAL;
+  hipStream_t s = (hipStream_t)stream;
+  if (S)
+    HIP_TRY(c, hipMemcpyAsync(S, c->S, 9 * c->dims.N * sizeof(double), hipMemcpyDeviceToDevice, s));
+  if (jinv)
+    HIP_TRY(c, hipMemcpyAsync(jinv, c->jinv, c->dims.N * sizeof(double), hipMemcpyDeviceToDevice, s));
+  return LES_OK;
+}
+
+long long les_updated_nodes(const les_ctx* c) { return c ? c->n_updated : 0; }
+
+void les_destroy(les_ctx* c) {
+  if (!c) return;
+  (void)hipDeviceSynchronize();
+  free_ctx(c);
+  delete c;
+}
+
+const char* les_last_error(const les_ctx* c) { return c ? c->err.c_str() : "null context"; }
+
+}  // extern "C"

@@ -1,0 +1,206 @@
+"""Python binding of liblesmi.so (C ABI in include/lesmi.h).
+
+Argument marshalling only: every step of the residual, boundary conditions and time
+stepping runs in the library's HIP kernels. Device arrays are torch float64 CUDA (ROCm)
+tensors, used purely as device memory; the stream is torch's current stream unless one
+is given. There is no CPU fallback: if the library is missing or the GPU is absent the
+calls raise.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import re
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "liblesmi.so")
+HEADER = os.path.join(os.path.dirname(_HERE), "include", "lesmi.h")
+
+LES_OK, LES_EINVAL, LES_ENOMEM, LES_EGRID, LES_EHIP, LES_ENONFINITE, LES_ESTATE = \
+    0, -1, -2, -3, -4, -5, -6
+STATUS_NAMES = {0: "LES_OK", -1: "LES_EINVAL", -2: "LES_ENOMEM", -3: "LES_EGRID",
+                -4: "LES_EHIP", -5: "LES_ENONFINITE", -6: "LES_ESTATE"}
+
+
+class LesError(RuntimeError):
+    def __init__(self, code, what, msg=""):
+        super().__init__(f"{what}: {STATUS_NAMES.get(code, code)} {msg}")
+        self.code = code
+
+
+class les_params(ctypes.Structure):
+    _fields_ = [
+        ("ni", ctypes.c_int), ("nj", ctypes.c_int), ("nk", ctypes.c_int),
+        ("bc", ctypes.c_int * 6),
+        ("period_shift", ctypes.c_double * 9),
+        ("gamma", ctypes.c_double), ("prandtl", ctypes.c_double),
+        ("prandtl_sgs", ctypes.c_double), ("re_acoustic", ctypes.c_double),
+        ("suth_s1", ctypes.c_double), ("cs", ctypes.c_double),
+        ("k2", ctypes.c_double), ("k4", ctypes.c_double),
+        ("mach_jet", ctypes.c_double), ("jet_radius", ctypes.c_double),
+        ("rho_inf", ctypes.c_double), ("u_inf", ctypes.c_double * 3),
+        ("p_inf", ctypes.c_double),
+        ("precision", ctypes.c_int), ("closure", ctypes.c_int),
+    ]
+
+
+_lib = None
+
+
+def load():
+    """Load liblesmi.so; raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is not built; run __graft_entry__.build() or "
+                               "python paper_2212_12365_amd/build.py")
+        lib = ctypes.CDLL(LIB_PATH)
+        vp, dp = ctypes.c_void_p, ctypes.POINTER(ctypes.c_double)
+        lib.les_init_grid.argtypes = [ctypes.POINTER(les_params), dp, ctypes.POINTER(vp)]
+        lib.les_residual.argtypes = [vp, vp, vp, vp]
+        lib.les_step.argtypes = [vp, vp, ctypes.c_int, ctypes.c_double, ctypes.c_double, dp, vp]
+        lib.les_sgs_viscosity.argtypes = [vp, vp, vp, vp]
+        lib.les_apply_bc.argtypes = [vp, vp, vp]
+        lib.les_diagnostics.argtypes = [vp, vp, dp, vp]
+        lib.les_get_metrics.argtypes = [vp, vp, vp, vp]
+        lib.les_updated_nodes.argtypes = [vp]
+        lib.les_updated_nodes.restype = ctypes.c_longlong
+        lib.les_destroy.argtypes = [vp]
+        lib.les_destroy.restype = None
+        lib.les_last_error.argtypes = [vp]
+        lib.les_last_error.restype = ctypes.c_char_p
+        _lib = lib
+    return _lib
+
+
+def header_functions():
+    """Names of the functions include/lesmi.h declares."""
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(les_[a-z0-9_]+)\s*\(", text)))
+
+
+def make_params(p):
+    s = les_params()
+    s.ni, s.nj, s.nk = p.ni, p.nj, p.nk
+    for i in range(6):
+        s.bc[i] = int(p.bc[i])
+    shift = np.asarray(p.period_shift, dtype=np.float64).reshape(9)
+    for i in range(9):
+        s.period_shift[i] = float(shift[i])
+    s.gamma, s.prandtl, s.prandtl_sgs = p.gamma, p.prandtl, p.prandtl_sgs
+    s.re_acoustic, s.suth_s1, s.cs, s.k2, s.k4 = p.re_acoustic, p.suth_s1, p.cs, p.k2, p.k4
+    s.mach_jet, s.jet_radius, s.rho_inf = p.mach_jet, p.jet_radius, p.rho_inf
+    for i in range(3):
+        s.u_inf[i] = float(p.u_inf[i])
+    s.p_inf = p.p_inf
+    s.precision, s.closure = int(p.precision), int(p.closure)
+    return s
+
+
+def _stream(stream):
+    import torch
+    if stream is None:
+        return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+    return ctypes.c_void_p(getattr(stream, "cuda_stream", stream))
+
+
+def _dev(t, n_expected, what):
+    import torch
+    if not isinstance(t, torch.Tensor) or not t.is_cuda or t.dtype != torch.float64 \
+            or not t.is_contiguous() or t.numel() != n_expected:
+        raise ValueError(f"{what}: expected a contiguous float64 GPU tensor of "
+                         f"{n_expected} elements")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+class Context:
+    """One grid and parameter set on the current GPU (les_init_grid .. les_destroy)."""
+
+    def __init__(self, params, xyz, allow_bad_grid=False):
+        self.lib = load()
+        self.params = params
+        self.n = params.ni * params.nj * params.nk
+        self.shape = params.shape
+        self._s = make_params(params)
+        xyz = np.ascontiguousarray(xyz, dtype=np.float64)
+        if xyz.size != 3 * self.n:
+            raise ValueError("xyz must hold 3 * ni * nj * nk values")
+        h = ctypes.c_void_p()
+        rc = self.lib.les_init_grid(ctypes.byref(self._s),
+                                    xyz.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                    ctypes.byref(h))
+        self.handle = h
+        self.init_status = rc
+        if rc != LES_OK and not (rc == LES_EGRID and allow_bad_grid and h.value):
+            msg = self.lib.les_last_error(h).decode() if h.value else ""
+            if h.value:
+                self.lib.les_destroy(h)
+                self.handle = ctypes.c_void_p()
+            raise LesError(rc, "les_init_grid", msg)
+
+    def _check(self, rc, what):
+        if rc != LES_OK:
+            raise LesError(rc, what, self.lib.les_last_error(self.handle).decode())
+
+    def residual(self, q, rhs=None, stream=None):
+        import torch
+        if rhs is None:
+            rhs = torch.empty_like(q)
+        self._check(self.lib.les_residual(self.handle, _dev(q, 5 * self.n, "q"),
+                                          _dev(rhs, 5 * self.n, "rhs"), _stream(stream)),
+                    "les_residual")
+        return rhs
+
+    def step(self, q, nsteps, cfl=0.5, dt_fixed=0.0, stream=None):
+        dt = ctypes.c_double(0.0)
+        self._check(self.lib.les_step(self.handle, _dev(q, 5 * self.n, "q"), int(nsteps),
+                                      float(cfl), float(dt_fixed), ctypes.byref(dt),
+                                      _stream(stream)), "les_step")
+        return dt.value
+
+    def sgs_viscosity(self, q, mu_t=None, stream=None):
+        import torch
+        if mu_t is None:
+            mu_t = torch.empty(self.shape, dtype=torch.float64, device=q.device)
+        self._check(self.lib.les_sgs_viscosity(self.handle, _dev(q, 5 * self.n, "q"),
+                                               _dev(mu_t, self.n, "mu_t"), _stream(stream)),
+                    "les_sgs_viscosity")
+        return mu_t
+
+    def apply_bc(self, q, stream=None):
+        self._check(self.lib.les_apply_bc(self.handle, _dev(q, 5 * self.n, "q"),
+                                          _stream(stream)), "les_apply_bc")
+        return q
+
+    def diagnostics(self, q, stream=None):
+        out = np.zeros(6)
+        self._check(self.lib.les_diagnostics(self.handle, _dev(q, 5 * self.n, "q"),
+                                             out.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                             _stream(stream)), "les_diagnostics")
+        return out
+
+    def metrics(self, stream=None):
+        import torch
+        S = torch.empty((9,) + self.shape, dtype=torch.float64, device="cuda")
+        jinv = torch.empty(self.shape, dtype=torch.float64, device="cuda")
+        self._check(self.lib.les_get_metrics(self.handle, _dev(S, 9 * self.n, "S"),
+                                             _dev(jinv, self.n, "jinv"), _stream(stream)),
+                    "les_get_metrics")
+        return S, jinv
+
+    def updated_nodes(self):
+        return int(self.lib.les_updated_nodes(self.handle))
+
+    def close(self):
+        if self.handle and self.handle.value:
+            self.lib.les_destroy(self.handle)
+            self.handle = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
