@@ -123,6 +123,22 @@ int les_get_metrics(les_ctx* ctx, double* S, double* jinv, void* stream);
 /* Number of nodes updated by the time integration (those not on a non-periodic face). */
 long long les_updated_nodes(const les_ctx* ctx);
 
+/* Launch tuning of the stage kernel: `tile` indexes the table of thread-tile shapes
+ * (0 .. les_tuning_count()-1, named by les_tuning_name), `kmin` is the smallest number of
+ * z-planes one block marches through. Results do not depend on the choice (the same
+ * arithmetic runs in the same order for every node); only the speed does. */
+int les_set_tuning(les_ctx* ctx, int tile, int kmin);
+int les_tuning_count(void);
+const char* les_tuning_name(int tile);
+
+/* Instrumentation: with enable != 0, les_step records a HIP event on its stream before and
+ * after every Runge-Kutta stage kernel launch (the residual and the stage update, boundary
+ * conditions excluded). les_profile_read waits for the last recorded event, returns the
+ * summed stage-kernel time in milliseconds and the number of timed launches since the last
+ * read (or since les_profile), and resets the record. */
+int les_profile(les_ctx* ctx, int enable);
+int les_profile_read(les_ctx* ctx, double* total_ms, long long* launches);
+
 void les_destroy(les_ctx* ctx);
 const char* les_last_error(const les_ctx* ctx);
 

@@ -5,6 +5,7 @@
 
 #include <cstdint>
 #include <string>
+#include <vector>
 
 #include "../../include/lesmi.h"
 #include "les_device.h"
@@ -59,16 +60,21 @@ struct les_ctx {
   double* qa = nullptr;
   double* qb = nullptr;
 
-  // Work arrays of the residual pipeline.
-  double* prim = nullptr;   // [7][N]: rho u v w p T mu
-  double* node = nullptr;   // [19][N]: dq[3][4], mut, lbar[3], nu[3]
-  double* flux = nullptr;   // [3][5][N] face fluxes
-  double* rhs = nullptr;    // [5][N]
+  // Node records of the stage kernels [kRecCount][N].
+  double* rec = nullptr;
+  // Stage kernel launch shape (index into the tile table) and smallest z-chunk depth.
+  int tile = 0;
+  int kmin = 8;
 
   // Scalars: dt, min-ratio bits, status flags, reduction partials.
   double* d_dt = nullptr;
-  unsigned long long* d_minbits = nullptr;
+  double* d_dtpart = nullptr;   // per-block minima of the time-step reduction
   int* d_flag = nullptr;
-  double* d_partial = nullptr;  // [kMaxPartials * 6]
+  double* d_partial = nullptr;  // [kMaxPartials * 7]
   double* d_diag = nullptr;     // [6]
+
+  // Optional timing of the stage kernel launches with HIP events on the caller's stream.
+  bool prof = false;
+  std::vector<hipEvent_t> ev;
+  size_t nrec = 0;
 };

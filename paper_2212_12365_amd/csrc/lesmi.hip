@@ -11,6 +11,7 @@
 #include <vector>
 
 #include "les_common.h"
+#include "les_stage.h"
 
 using namespace lesmi;
 
@@ -21,6 +22,11 @@ constexpr int kMaxPartials = 4096;
 
 inline unsigned grid_for(long long n, int block = kBlock) {
   return (unsigned)((n + block - 1) / block);
+}
+
+// 64 x 4 thread blocks over (i, j), one z-plane per grid layer.
+inline dim3 node_grid(const Dims& D) {
+  return dim3((D.n[0] + 63) / 64, (D.n[1] + 3) / 4, D.n[2]);
 }
 
 // ---------------------------------------------------------------------------------------
@@ -159,234 +165,6 @@ __global__ void k_bc_normals(Dims D, const double* __restrict__ S, BcData B) {
 }
 
 // ---------------------------------------------------------------------------------------
-// Residual pipeline (paper, Spatial Discretization).
-// ---------------------------------------------------------------------------------------
-__global__ void k_prims(Dims D, Phys P, const double* __restrict__ q, double* __restrict__ pr) {
-  long long id = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (id >= D.N) return;
-  long long N = D.N;
-  Prim s = prim_from_q(q[id], q[N + id], q[2 * N + id], q[3 * N + id], q[4 * N + id], P);
-  pr[id] = s.rho;
-  pr[N + id] = s.u;
-  pr[2 * N + id] = s.v;
-  pr[3 * N + id] = s.w;
-  pr[4 * N + id] = s.p;
-  pr[5 * N + id] = s.T;
-  pr[6 * N + id] = sutherland(s.T, P);
-}
-
-// Difference of field f along e at (i,j,k): centred, periodic wrap, one-sided at the ends.
-__device__ __forceinline__ double dnode(const Dims& D, const double* f, int e, int i, int j,
-                                        int k) {
-  int ix[3] = {i, j, k};
-  int m = ix[e], n = D.n[e];
-  int a[3] = {i, j, k}, b[3] = {i, j, k}, c[3] = {i, j, k};
-  if (D.per[e]) {
-    a[e] = (m + 1 == n) ? 0 : m + 1;
-    b[e] = (m == 0) ? n - 1 : m - 1;
-    return 0.5 * (f[nid(D, a[0], a[1], a[2])] - f[nid(D, b[0], b[1], b[2])]);
-  }
-  if (m == 0) {
-    b[e] = 1;
-    c[e] = 2;
-    return 0.5 * (-3.0 * f[nid(D, a[0], a[1], a[2])] + 4.0 * f[nid(D, b[0], b[1], b[2])] -
-                  f[nid(D, c[0], c[1], c[2])]);
-  }
-  if (m == n - 1) {
-    b[e] = n - 2;
-    c[e] = n - 3;
-    return 0.5 * (3.0 * f[nid(D, a[0], a[1], a[2])] - 4.0 * f[nid(D, b[0], b[1], b[2])] +
-                  f[nid(D, c[0], c[1], c[2])]);
-  }
-  a[e] = m + 1;
-  b[e] = m - 1;
-  return 0.5 * (f[nid(D, a[0], a[1], a[2])] - f[nid(D, b[0], b[1], b[2])]);
-}
-
-// Node quantities: differences of (u, v, w, T), eddy viscosity, scaled spectral radii and
-// pressure sensors (paper, Subgrid Scale Viscosity; Spatial Discretization).
-// Layout of `node`: [e*4 + v] = delta_e var_v (12), [12] mu_t, [13..15] Lb_d, [16..18] nu_d.
-__global__ void k_node(Dims D, Phys P, const double* __restrict__ pr,
-                       const double* __restrict__ S, const double* __restrict__ jinv,
-                       double* __restrict__ node) {
-  long long id = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (id >= D.N) return;
-  long long N = D.N;
-  int i = (int)(id % D.n[0]);
-  int j = (int)((id / D.n[0]) % D.n[1]);
-  int k = (int)(id / ((long long)D.n[0] * D.n[1]));
-  double dq[3][3];
-  for (int e = 0; e < 3; ++e) {
-    for (int v = 0; v < 4; ++v) {
-      double val = dnode(D, pr + (1 + (v < 3 ? v : 4)) * N, e, i, j, k);
-      node[(long long)(e * 4 + v) * N + id] = val;
-      if (v < 3) dq[e][v] = val;
-    }
-  }
-  double s[9];
-  for (int c = 0; c < 9; ++c) s[c] = S[(long long)c * N + id];
-  double rho = pr[id], u = pr[N + id], v = pr[2 * N + id], w = pr[3 * N + id];
-  node[12 * N + id] = smagorinsky(s, dq, rho, jinv[id], P);
-  double a = sqrt(pr[5 * N + id]);
-  double l0 = spectral(s[0], s[1], s[2], u, v, w, a);
-  double l1 = spectral(s[3], s[4], s[5], u, v, w, a);
-  double l2 = spectral(s[6], s[7], s[8], u, v, w, a);
-  double lb[3];
-  scaled_radii(l0, l1, l2, lb);
-  node[13 * N + id] = lb[0];
-  node[14 * N + id] = lb[1];
-  node[15 * N + id] = lb[2];
-  const double* p = pr + 4 * N;
-  int ix[3] = {i, j, k};
-  for (int e = 0; e < 3; ++e) {
-    int c[3] = {i, j, k};
-    int n = D.n[e];
-    if (!D.per[e]) {  // boundary nodes take the sensor of the adjacent interior node
-      if (ix[e] == 0) c[e] = 1;
-      if (ix[e] == n - 1) c[e] = n - 2;
-    }
-    int a1[3] = {c[0], c[1], c[2]}, b1[3] = {c[0], c[1], c[2]};
-    a1[e] = (c[e] + 1 == n) ? 0 : c[e] + 1;
-    b1[e] = (c[e] == 0) ? n - 1 : c[e] - 1;
-    node[(long long)(16 + e) * N + id] =
-        sensor(p[nid(D, b1[0], b1[1], b1[2])], p[nid(D, c[0], c[1], c[2])],
-               p[nid(D, a1[0], a1[1], a1[2])]);
-  }
-}
-
-// Total numerical flux on the face between node A and its + neighbour along d:
-// H = (F_A + F_B)/2 - D - F_v (paper, Spatial Discretization, interface flux with the
-// Turkel-Vatsa terms; viscous flux from the two nodes of the interface).
-template <int d>
-__global__ void k_face(Dims D, Phys P, const double* __restrict__ q,
-                       const double* __restrict__ pr, const double* __restrict__ node,
-                       const double* __restrict__ S, const double* __restrict__ jinv,
-                       double* __restrict__ H) {
-  long long a = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (a >= D.N) return;
-  long long N = D.N;
-  int ix[3];
-  ix[0] = (int)(a % D.n[0]);
-  ix[1] = (int)((a / D.n[0]) % D.n[1]);
-  ix[2] = (int)(a / ((long long)D.n[0] * D.n[1]));
-  int n = D.n[d], m = ix[d];
-  if (!D.per[d] && m == n - 1) {
-    for (int c = 0; c < 5; ++c) H[(long long)c * N + a] = 0.0;
-    return;
-  }
-  auto at = [&](int off) {
-    int t[3] = {ix[0], ix[1], ix[2]};
-    int mm = m + off;
-    if (mm < 0) mm += n;
-    if (mm >= n) mm -= n;
-    t[d] = mm;
-    return nid(D, t[0], t[1], t[2]);
-  };
-  long long b = at(1);
-  // Inviscid node fluxes.
-  double qa[5], qbv[5], FA[5], FB[5];
-  for (int c = 0; c < 5; ++c) {
-    qa[c] = q[(long long)c * N + a];
-    qbv[c] = q[(long long)c * N + b];
-  }
-  Prim sa{pr[a], pr[N + a], pr[2 * N + a], pr[3 * N + a], pr[4 * N + a], pr[5 * N + a]};
-  Prim sb{pr[b], pr[N + b], pr[2 * N + b], pr[3 * N + b], pr[4 * N + b], pr[5 * N + b]};
-  inviscid_flux(S[(3 * d) * N + a], S[(3 * d + 1) * N + a], S[(3 * d + 2) * N + a], qa, sa, FA);
-  inviscid_flux(S[(3 * d) * N + b], S[(3 * d + 1) * N + b], S[(3 * d + 2) * N + b], qbv, sb,
-                FB);
-  // Dissipated vector W = Q + (0,0,0,0,p) and its differences; at the first and last face of
-  // a non-periodic direction (Delta W)_outside = -(Delta W)_inside.
-  auto Wv = [&](long long id, int c) {
-    double v = q[(long long)c * N + id];
-    if (c == 4) v += pr[4 * N + id];
-    return v;
-  };
-  double dW[5], d3W[5];
-  if (D.per[d] || (m > 0 && m < n - 2)) {
-    long long am = at(-1), bp = at(2);
-    for (int c = 0; c < 5; ++c) {
-      double wA = Wv(a, c), wB = Wv(b, c);
-      dW[c] = wB - wA;
-      d3W[c] = Wv(bp, c) - 3.0 * wB + 3.0 * wA - Wv(am, c);
-    }
-  } else if (m == 0) {
-    long long bp = at(2);
-    for (int c = 0; c < 5; ++c) {
-      double wA = Wv(a, c), wB = Wv(b, c);
-      dW[c] = wB - wA;
-      d3W[c] = (Wv(bp, c) - wB) - 3.0 * dW[c];
-    }
-  } else {  // m == n - 2
-    long long am = at(-1);
-    for (int c = 0; c < 5; ++c) {
-      double wA = Wv(a, c), wB = Wv(b, c);
-      dW[c] = wB - wA;
-      d3W[c] = -3.0 * dW[c] + (wA - Wv(am, c));
-    }
-  }
-  double lf = 0.5 * (node[(13 + d) * N + a] + node[(13 + d) * N + b]);
-  double Dd[5];
-  dissipation(lf, node[(16 + d) * N + a], node[(16 + d) * N + b], dW, d3W, P, Dd);
-  // Viscous flux: compact difference along d, averaged nodal differences across.
-  double Sf[9];
-  for (int c = 0; c < 9; ++c) Sf[c] = 0.5 * (S[(long long)c * N + a] + S[(long long)c * N + b]);
-  double jf = 0.5 * (jinv[a] + jinv[b]);
-  double gxi[4][3];
-  const int var_slot[4] = {1, 2, 3, 5};
-  for (int v = 0; v < 4; ++v)
-    for (int e = 0; e < 3; ++e) {
-      if (e == d)
-        gxi[v][e] = pr[var_slot[v] * N + b] - pr[var_slot[v] * N + a];
-      else
-        gxi[v][e] = 0.5 * (node[(long long)(e * 4 + v) * N + a] + node[(long long)(e * 4 + v) * N + b]);
-    }
-  double muf = 0.5 * (pr[6 * N + a] + pr[6 * N + b]);
-  double mutf = 0.5 * (node[12 * N + a] + node[12 * N + b]);
-  double ub[3] = {0.5 * (sa.u + sb.u), 0.5 * (sa.v + sb.v), 0.5 * (sa.w + sb.w)};
-  double Fv[5];
-  viscous_flux(Sf, jf, gxi, muf, mutf, ub, d, P, Fv);
-  Fv[0] = 0.0;
-  for (int c = 0; c < 5; ++c) H[(long long)c * N + a] = 0.5 * (FA[c] + FB[c]) - Dd[c] - Fv[c];
-}
-
-// RHS = sum_d (H_{+1/2} - H_{-1/2}) at updated nodes. Mode 0 writes rhs; mode 1 writes the
-// Runge-Kutta stage Q^(l) = Q^(0) - alpha dt J RHS (paper, Time Marching Method).
-__global__ void k_rhs(Dims D, const double* __restrict__ H, double* __restrict__ out,
-                      const double* __restrict__ q0, const double* __restrict__ jac,
-                      const double* __restrict__ dtp, double alpha, int mode) {
-  long long id = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (id >= D.N) return;
-  long long N = D.N;
-  int ix[3];
-  ix[0] = (int)(id % D.n[0]);
-  ix[1] = (int)((id / D.n[0]) % D.n[1]);
-  ix[2] = (int)(id / ((long long)D.n[0] * D.n[1]));
-  bool upd = is_updated(D, ix[0], ix[1], ix[2]);
-  if (!upd) {
-    if (mode == 0)
-      for (int c = 0; c < 5; ++c) out[(long long)c * N + id] = 0.0;
-    return;
-  }
-  long long prev[3];
-  for (int d = 0; d < 3; ++d) {
-    int t[3] = {ix[0], ix[1], ix[2]};
-    t[d] = (ix[d] == 0) ? D.n[d] - 1 : ix[d] - 1;
-    prev[d] = nid(D, t[0], t[1], t[2]);
-  }
-  double fac = 0.0;
-  if (mode == 1) fac = alpha * dtp[0] * jac[id];
-  for (int c = 0; c < 5; ++c) {
-    const double* Hc = H + (long long)c * N;
-    double r = 0.0;
-    for (int d = 0; d < 3; ++d) r += Hc[(long long)d * 5 * N + id] - Hc[(long long)d * 5 * N + prev[d]];
-    if (mode == 0)
-      out[(long long)c * N + id] = r;
-    else
-      out[(long long)c * N + id] = q0[(long long)c * N + id] - fac * r;
-  }
-}
-
-// ---------------------------------------------------------------------------------------
 // Boundary conditions (paper, Boundary Conditions).
 // ---------------------------------------------------------------------------------------
 
@@ -431,16 +209,28 @@ __device__ void farfield_state(const Phys& P, const BcData& B, const double* qe,
 }
 
 // Centreline means of the first ring, summed in k order (paper, Centerline Boundary
-// Condition).
-__global__ void k_axis_mean(Dims D, const double* __restrict__ q, double* __restrict__ axis) {
-  int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < 1 || i > D.n[0] - 2) return;
-  long long N = D.N;
-  for (int c = 0; c < 5; ++c) {
-    double s = 0.0;
-    for (int k = 0; k < D.n[2]; ++k) s += q[(long long)c * N + nid(D, i, 1, k)];
-    axis[(long long)c * D.n[0] + i] = s / (double)D.n[2];
+// Condition). One block per axial station i: the ring is staged through LDS in chunks and
+// five threads add it up sequentially, so the sum order is k = 0, 1, ..., nk-1.
+constexpr int kAxisChunk = 1024;
+__global__ void __launch_bounds__(256) k_axis_mean(Dims D, const double* __restrict__ q,
+                                                   double* __restrict__ axis) {
+  __shared__ double ring[5][kAxisChunk];
+  const int i = blockIdx.x + 1;  // 1 <= i <= ni - 2
+  const long long N = D.N;
+  const int nk = D.n[2];
+  double sum = 0.0;  // thread c < 5 accumulates component c
+  for (int kb = 0; kb < nk; kb += kAxisChunk) {
+    int len = min(kAxisChunk, nk - kb);
+    for (int t = threadIdx.x; t < 5 * len; t += blockDim.x) {
+      int c = t / len, k = kb + t % len;
+      ring[c][k - kb] = q[(long long)c * N + nid(D, i, 1, k)];
+    }
+    __syncthreads();
+    if (threadIdx.x < 5)
+      for (int k = 0; k < len; ++k) sum += ring[threadIdx.x][k];
+    __syncthreads();
   }
+  if (threadIdx.x < 5) axis[(long long)threadIdx.x * D.n[0] + i] = sum / (double)nk;
 }
 
 __device__ __forceinline__ void load_q(const double* q, long long N, long long id, double* o) {
@@ -538,56 +328,64 @@ __global__ void k_bc(Dims D, Phys P, BcData B, double* __restrict__ q) {
 }
 
 // ---------------------------------------------------------------------------------------
-// Time step: dt = CFL min over updated nodes of J^-1 / sum_d Lam_d. A positive double's
-// bit pattern orders like the value, so the minimum is an exact integer atomic minimum.
+// Time step: dt = CFL min over updated nodes of J^-1 / sum_d Lam_d; block minima, then one
+// block reduces them (min is exact whatever the order).
 // ---------------------------------------------------------------------------------------
-__global__ void k_dt_reset(unsigned long long* bits) { bits[0] = 0x7ff0000000000000ull; }
-
-__global__ void k_dt_partial(Dims D, Phys P, const double* __restrict__ q,
-                             const double* __restrict__ S, const double* __restrict__ jinv,
-                             unsigned long long* __restrict__ bits, int* __restrict__ flag) {
-  __shared__ double red[kBlock];
-  long long id = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+__global__ void __launch_bounds__(256) k_dt_partial(Dims D, Phys P, const double* __restrict__ q,
+                                                    const double* __restrict__ S,
+                                                    const double* __restrict__ jinv,
+                                                    double* __restrict__ part,
+                                                    int* __restrict__ flag) {
+  __shared__ double red[256];
+  const int i = blockIdx.x * 64 + threadIdx.x, j = blockIdx.y * 4 + threadIdx.y, k = blockIdx.z;
+  const int tid = threadIdx.x + 64 * threadIdx.y;
   double r = INFINITY;
-  if (id < D.N) {
-    int i = (int)(id % D.n[0]);
-    int j = (int)((id / D.n[0]) % D.n[1]);
-    int k = (int)(id / ((long long)D.n[0] * D.n[1]));
-    if (is_updated(D, i, j, k)) {
-      long long N = D.N;
-      Prim s = prim_from_q(q[id], q[N + id], q[2 * N + id], q[3 * N + id], q[4 * N + id], P);
-      double a = sqrt(s.T);
-      double l = spectral(S[id], S[N + id], S[2 * N + id], s.u, s.v, s.w, a) +
-                 spectral(S[3 * N + id], S[4 * N + id], S[5 * N + id], s.u, s.v, s.w, a) +
-                 spectral(S[6 * N + id], S[7 * N + id], S[8 * N + id], s.u, s.v, s.w, a);
-      r = jinv[id] / l;
-      if (!(s.rho > 0.0) || !(s.p > 0.0) || !isfinite(r)) atomicOr(flag, 2);
-    }
+  if (i < D.n[0] && j < D.n[1] && is_updated(D, i, j, k)) {
+    const int N = (int)D.N;
+    const int id = i + D.n[0] * (j + D.n[1] * k);
+    Prim s = prim_from_q(q[id], q[N + id], q[2 * N + id], q[3 * N + id], q[4 * N + id], P);
+    double a = sqrt(s.T);
+    double l = spectral(S[id], S[N + id], S[2 * N + id], s.u, s.v, s.w, a) +
+               spectral(S[3 * N + id], S[4 * N + id], S[5 * N + id], s.u, s.v, s.w, a) +
+               spectral(S[6 * N + id], S[7 * N + id], S[8 * N + id], s.u, s.v, s.w, a);
+    r = jinv[id] / l;
+    if (!(s.rho > 0.0) || !(s.p > 0.0) || !isfinite(r)) atomicOr(flag, 2);
   }
+  red[tid] = r;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if (tid < o) red[tid] = fmin(red[tid], red[tid + o]);
+    __syncthreads();
+  }
+  if (tid == 0)
+    part[blockIdx.x + gridDim.x * (blockIdx.y + gridDim.y * blockIdx.z)] = red[0];
+}
+
+// dt = CFL times the minimum of the block minima (exact in any order).
+__global__ void __launch_bounds__(256) k_dt_final(const double* __restrict__ part, int nparts,
+                                                  double cfl, double* __restrict__ dt) {
+  __shared__ double red[256];
+  double r = INFINITY;
+  for (int b = threadIdx.x; b < nparts; b += 256) r = fmin(r, part[b]);
   red[threadIdx.x] = r;
   __syncthreads();
-  for (int o = kBlock / 2; o > 0; o >>= 1) {
+  for (int o = 128; o > 0; o >>= 1) {
     if ((int)threadIdx.x < o) red[threadIdx.x] = fmin(red[threadIdx.x], red[threadIdx.x + o]);
     __syncthreads();
   }
-  if (threadIdx.x == 0 && red[0] < INFINITY) {
-    atomicMin(bits, (unsigned long long)__double_as_longlong(red[0]));
-  }
-}
-
-__global__ void k_dt_final(const unsigned long long* __restrict__ bits, double cfl,
-                           double* __restrict__ dt) {
-  dt[0] = cfl * __longlong_as_double((long long)bits[0]);
+  if (threadIdx.x == 0) dt[0] = cfl * red[0];
 }
 
 __global__ void k_set_scalar(double* p, double v) { p[0] = v; }
 __global__ void k_set_int(int* p, int v) { p[0] = v; }
 
 // Non-finite or non-positive density/pressure anywhere in q sets flag bit 2.
-__global__ void k_check(Dims D, Phys P, const double* __restrict__ q, int* __restrict__ flag) {
-  long long id = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (id >= D.N) return;
-  long long N = D.N;
+__global__ void __launch_bounds__(256) k_check(Dims D, Phys P, const double* __restrict__ q,
+                                               int* __restrict__ flag) {
+  const int i = blockIdx.x * 64 + threadIdx.x, j = blockIdx.y * 4 + threadIdx.y, k = blockIdx.z;
+  if (i >= D.n[0] || j >= D.n[1]) return;
+  const int N = (int)D.N;
+  const int id = i + D.n[0] * (j + D.n[1] * k);
   Prim s = prim_from_q(q[id], q[N + id], q[2 * N + id], q[3 * N + id], q[4 * N + id], P);
   bool ok = s.rho > 0.0 && s.p > 0.0 && isfinite(s.u) && isfinite(s.v) && isfinite(s.w) &&
             isfinite(q[4 * N + id]);
@@ -735,33 +533,64 @@ int dev_alloc(les_ctx* c, T** p, size_t count) {
 
 void free_ctx(les_ctx* c) {
   if (!c) return;
+  for (hipEvent_t e : c->ev) (void)hipEventDestroy(e);
+  c->ev.clear();
   void* ptrs[] = {c->S, c->jinv, c->jac, c->bc.nff, c->bc.nin, c->bc.nex, c->bc.jetmask,
-                  c->bc.axis, c->qa, c->qb, c->prim, c->node, c->flux, c->rhs, c->d_dt,
-                  c->d_minbits, c->d_flag, c->d_partial, c->d_diag};
+                  c->bc.axis, c->qa, c->qb, c->rec, c->d_dt, c->d_dtpart, c->d_flag,
+                  c->d_partial, c->d_diag};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
 }
 
-// Residual pipeline on q into the face-flux buffer.
-int run_fluxes(les_ctx* c, const double* q, hipStream_t s) {
-  const Dims& D = c->dims;
-  unsigned g = grid_for(D.N);
-  hipLaunchKernelGGL(k_prims, dim3(g), dim3(kBlock), 0, s, D, c->phys, q, c->prim);
-  hipLaunchKernelGGL(k_node, dim3(g), dim3(kBlock), 0, s, D, c->phys, c->prim, c->S, c->jinv,
-                     c->node);
-  hipLaunchKernelGGL(k_face<0>, dim3(g), dim3(kBlock), 0, s, D, c->phys, q, c->prim, c->node,
-                     c->S, c->jinv, c->flux);
-  hipLaunchKernelGGL(k_face<1>, dim3(g), dim3(kBlock), 0, s, D, c->phys, q, c->prim, c->node,
-                     c->S, c->jinv, c->flux + 5 * D.N);
-  hipLaunchKernelGGL(k_face<2>, dim3(g), dim3(kBlock), 0, s, D, c->phys, q, c->prim, c->node,
-                     c->S, c->jinv, c->flux + 10 * D.N);
-  return launch_check(c, "residual kernels");
+StageArgs stage_args(les_ctx* c, const double* q) {
+  StageArgs A{};
+  A.D = c->dims;
+  A.P = c->phys;
+  A.q = q;
+  A.S = c->S;
+  A.jinv = c->jinv;
+  A.jac = c->jac;
+  A.rec = c->rec;
+  A.tile = c->tile;
+  A.kmin = c->kmin;
+  return A;
+}
+
+// One residual evaluation: node records, then faces and flux differences with either the
+// residual (mode 0) or the Runge-Kutta stage update (mode 1) as the epilogue.
+int run_stage(les_ctx* c, const double* q, int mode, double* out, const double* q0,
+              double alpha, hipStream_t s) {
+  StageArgs A = stage_args(c, q);
+  A.mode = mode;
+  A.out = out;
+  A.q0 = q0;
+  A.dt = c->d_dt;
+  A.alpha = alpha;
+  hipError_t e = launch_nodes(A, s);
+  if (e == hipSuccess) e = launch_stage(A, s);
+  if (e != hipSuccess) {
+    c->err = std::string("stage kernels: ") + hipGetErrorString(e);
+    return LES_EHIP;
+  }
+  return LES_OK;
+}
+
+// Records the next event of the profiling ring (start/end pairs around each stage).
+int prof_mark(les_ctx* c, hipStream_t s) {
+  if (!c->prof) return LES_OK;
+  if (c->nrec == c->ev.size()) {
+    hipEvent_t e;
+    HIP_TRY(c, hipEventCreate(&e));
+    c->ev.push_back(e);
+  }
+  HIP_TRY(c, hipEventRecord(c->ev[c->nrec++], s));
+  return LES_OK;
 }
 
 int run_bc(les_ctx* c, double* q, hipStream_t s) {
   const Dims& D = c->dims;
   if (!D.jet) return LES_OK;
-  hipLaunchKernelGGL(k_axis_mean, dim3(grid_for(D.n[0])), dim3(kBlock), 0, s, D, q, c->bc.axis);
+  hipLaunchKernelGGL(k_axis_mean, dim3(D.n[0] - 2), dim3(kBlock), 0, s, D, q, c->bc.axis);
   long long nbc = 2LL * (D.n[0] - 2) * D.n[2] + 2LL * D.n[1] * D.n[2];
   hipLaunchKernelGGL(k_bc, dim3(grid_for(nbc)), dim3(kBlock), 0, s, D, c->phys, c->bc, q);
   return launch_check(c, "boundary kernels");
@@ -797,9 +626,9 @@ int les_init_grid(const les_params* params, const double* xyz, les_ctx** out) {
   };
   if (dev_alloc(c, &c->S, 9 * N) || dev_alloc(c, &c->jinv, N) || dev_alloc(c, &c->jac, N) ||
       dev_alloc(c, &c->qa, 5 * N) || dev_alloc(c, &c->qb, 5 * N) ||
-      dev_alloc(c, &c->prim, 7 * N) || dev_alloc(c, &c->node, 19 * N) ||
-      dev_alloc(c, &c->flux, 15 * N) || dev_alloc(c, &c->rhs, 5 * N) ||
-      dev_alloc(c, &c->d_dt, 1) || dev_alloc(c, &c->d_minbits, 1) ||
+      dev_alloc(c, &c->rec, (size_t)kRecCount * N) ||
+      dev_alloc(c, &c->d_dt, 1) ||
+      dev_alloc(c, &c->d_dtpart, (size_t)node_grid(D).x * node_grid(D).y * node_grid(D).z) ||
       dev_alloc(c, &c->d_flag, 1) || dev_alloc(c, &c->d_partial, 7 * kMaxPartials) ||
       dev_alloc(c, &c->d_diag, 8) || dev_alloc(c, &c->bc.nff, 3LL * ni * nk) ||
       dev_alloc(c, &c->bc.nin, 3LL * nj * nk) || dev_alloc(c, &c->bc.nex, 3LL * nj * nk) ||
@@ -853,25 +682,19 @@ int les_init_grid(const les_params* params, const double* xyz, les_ctx** out) {
 
 int les_residual(les_ctx* c, const double* q, double* rhs, void* stream) {
   if (!c || !q || !rhs) return fail(c, LES_EINVAL, "null argument");
-  hipStream_t s = (hipStream_t)stream;
-  int rc = run_fluxes(c, q, s);
-  if (rc) return rc;
-  hipLaunchKernelGGL(k_rhs, dim3(grid_for(c->dims.N)), dim3(kBlock), 0, s, c->dims, c->flux,
-                     rhs, (const double*)nullptr, (const double*)nullptr, (const double*)nullptr,
-                     0.0, 0);
-  return launch_check(c, "k_rhs");
+  return run_stage(c, q, 0, rhs, nullptr, 0.0, (hipStream_t)stream);
 }
 
 int les_sgs_viscosity(les_ctx* c, const double* q, double* mu_t, void* stream) {
   if (!c || !q || !mu_t) return fail(c, LES_EINVAL, "null argument");
-  hipStream_t s = (hipStream_t)stream;
-  const Dims& D = c->dims;
-  unsigned g = grid_for(D.N);
-  hipLaunchKernelGGL(k_prims, dim3(g), dim3(kBlock), 0, s, D, c->phys, q, c->prim);
-  hipLaunchKernelGGL(k_node, dim3(g), dim3(kBlock), 0, s, D, c->phys, c->prim, c->S, c->jinv,
-                     c->node);
-  hipLaunchKernelGGL(k_copy, dim3(g), dim3(kBlock), 0, s, D.N, c->node + 12 * D.N, mu_t);
-  return launch_check(c, "sgs kernels");
+  StageArgs A = stage_args(c, q);
+  A.mut_out = mu_t;
+  hipError_t e = launch_nodes(A, (hipStream_t)stream);
+  if (e != hipSuccess) {
+    c->err = std::string("k_nodes: ") + hipGetErrorString(e);
+    return LES_EHIP;
+  }
+  return LES_OK;
 }
 
 int les_apply_bc(les_ctx* c, double* q, void* stream) {
@@ -886,30 +709,32 @@ int les_step(les_ctx* c, double* q, int nsteps, double cfl, double dt_fixed, dou
   static const double alpha[5] = {0.25, 1.0 / 6.0, 0.375, 0.5, 1.0};
   hipStream_t s = (hipStream_t)stream;
   const Dims& D = c->dims;
-  unsigned g = grid_for(D.N);
   hipLaunchKernelGGL(k_set_int, dim3(1), dim3(1), 0, s, c->d_flag, 0);
   for (int n = 0; n < nsteps; ++n) {
     if (cfl > 0.0) {
-      hipLaunchKernelGGL(k_dt_reset, dim3(1), dim3(1), 0, s, c->d_minbits);
-      hipLaunchKernelGGL(k_dt_partial, dim3(g), dim3(kBlock), 0, s, D, c->phys, q, c->S,
-                         c->jinv, c->d_minbits, c->d_flag);
-      hipLaunchKernelGGL(k_dt_final, dim3(1), dim3(1), 0, s, c->d_minbits, cfl, c->d_dt);
+      dim3 ng = node_grid(D);
+      hipLaunchKernelGGL(k_dt_partial, ng, dim3(64, 4), 0, s, D, c->phys, q, c->S, c->jinv,
+                         c->d_dtpart, c->d_flag);
+      hipLaunchKernelGGL(k_dt_final, dim3(1), dim3(256), 0, s, c->d_dtpart,
+                         (int)(ng.x * ng.y * ng.z), cfl, c->d_dt);
     } else {
       hipLaunchKernelGGL(k_set_scalar, dim3(1), dim3(1), 0, s, c->d_dt, dt_fixed);
     }
     const double* in = q;
     for (int l = 0; l < 5; ++l) {
       double* outb = (l == 4) ? q : ((l % 2 == 0) ? c->qa : c->qb);
-      int rc = run_fluxes(c, in, s);
+      int rc = prof_mark(c, s);
       if (rc) return rc;
-      hipLaunchKernelGGL(k_rhs, dim3(g), dim3(kBlock), 0, s, D, c->flux, outb, q, c->jac,
-                         c->d_dt, alpha[l], 1);
+      rc = run_stage(c, in, 1, outb, q, alpha[l], s);
+      if (rc) return rc;
+      rc = prof_mark(c, s);
+      if (rc) return rc;
       rc = run_bc(c, outb, s);
       if (rc) return rc;
       in = outb;
     }
   }
-  hipLaunchKernelGGL(k_check, dim3(g), dim3(kBlock), 0, s, D, c->phys, q, c->d_flag);
+  hipLaunchKernelGGL(k_check, node_grid(D), dim3(64, 4), 0, s, D, c->phys, q, c->d_flag);
   int rc = launch_check(c, "step kernels");
   if (rc) return rc;
   int flag = 0;
@@ -950,6 +775,42 @@ int les_get_metrics(les_ctx* c, double* S, double* jinv, void* stream) {
 }
 
 long long les_updated_nodes(const les_ctx* c) { return c ? c->n_updated : 0; }
+
+int les_set_tuning(les_ctx* c, int tile, int kmin) {
+  if (!c) return LES_EINVAL;
+  if (tile < 0 || tile >= kNumTiles || kmin < 1) return fail(c, LES_EINVAL, "bad tuning");
+  c->tile = tile;
+  c->kmin = kmin;
+  return LES_OK;
+}
+
+int les_tuning_count(void) { return kNumTiles; }
+
+const char* les_tuning_name(int tile) {
+  return (tile >= 0 && tile < kNumTiles) ? kTileNames[tile] : "";
+}
+
+int les_profile(les_ctx* c, int enable) {
+  if (!c) return LES_EINVAL;
+  c->prof = enable != 0;
+  c->nrec = 0;
+  return LES_OK;
+}
+
+int les_profile_read(les_ctx* c, double* total_ms, long long* launches) {
+  if (!c || !total_ms || !launches) return LES_EINVAL;
+  double tot = 0.0;
+  if (c->nrec >= 2) HIP_TRY(c, hipEventSynchronize(c->ev[c->nrec - 1]));
+  for (size_t r = 0; r + 1 < c->nrec; r += 2) {
+    float ms = 0.f;
+    HIP_TRY(c, hipEventElapsedTime(&ms, c->ev[r], c->ev[r + 1]));
+    tot += ms;
+  }
+  *total_ms = tot;
+  *launches = (long long)(c->nrec / 2);
+  c->nrec = 0;
+  return LES_OK;
+}
 
 void les_destroy(les_ctx* c) {
   if (!c) return;

@@ -67,6 +67,12 @@ def load():
         lib.les_get_metrics.argtypes = [vp, vp, vp, vp]
         lib.les_updated_nodes.argtypes = [vp]
         lib.les_updated_nodes.restype = ctypes.c_longlong
+        lib.les_set_tuning.argtypes = [vp, ctypes.c_int, ctypes.c_int]
+        lib.les_tuning_count.argtypes = []
+        lib.les_tuning_name.argtypes = [ctypes.c_int]
+        lib.les_tuning_name.restype = ctypes.c_char_p
+        lib.les_profile.argtypes = [vp, ctypes.c_int]
+        lib.les_profile_read.argtypes = [vp, dp, ctypes.POINTER(ctypes.c_longlong)]
         lib.les_destroy.argtypes = [vp]
         lib.les_destroy.restype = None
         lib.les_last_error.argtypes = [vp]
@@ -190,6 +196,23 @@ class Context:
                                              _dev(jinv, self.n, "jinv"), _stream(stream)),
                     "les_get_metrics")
         return S, jinv
+
+    def set_tuning(self, tile, kmin=8):
+        self._check(self.lib.les_set_tuning(self.handle, int(tile), int(kmin)), "les_set_tuning")
+
+    def tuning_names(self):
+        return [self.lib.les_tuning_name(t).decode() for t in range(self.lib.les_tuning_count())]
+
+    def profile(self, enable=True):
+        self._check(self.lib.les_profile(self.handle, int(bool(enable))), "les_profile")
+
+    def profile_read(self):
+        """(total stage-kernel milliseconds, number of timed launches) since the last read."""
+        ms = ctypes.c_double(0.0)
+        n = ctypes.c_longlong(0)
+        self._check(self.lib.les_profile_read(self.handle, ctypes.byref(ms), ctypes.byref(n)),
+                    "les_profile_read")
+        return ms.value, n.value
 
     def updated_nodes(self):
         return int(self.lib.les_updated_nodes(self.handle))
