@@ -63,7 +63,7 @@ struct les_ctx {
   // Node records of the stage kernels [kRecCount][N].
   double* rec = nullptr;
   // Stage kernel launch shape (index into the tile table) and smallest z-chunk depth.
-  int tile = 0;
+  int tile = 13;
   int kmin = 8;
 
   // Scalars: dt, min-ratio bits, status flags, reduction partials.

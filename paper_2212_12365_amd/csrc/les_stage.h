@@ -34,7 +34,7 @@ struct StageArgs {
   int kmin;   // smallest z-chunk depth (0 = default)
 };
 
-constexpr int kNumTiles = 10;
+constexpr int kNumTiles = 16;
 extern const char* const kTileNames[kNumTiles];
 
 hipError_t launch_nodes(const StageArgs& A, hipStream_t s);

@@ -381,6 +381,401 @@ k_stage(StageArgs A, int kchunk) {
   }
 }
 
+// ---------------------------------------------------------------------------------------
+// Plane-staged stage kernel. One block per TX x TY column tile marches through a chunk of
+// z-planes. Each plane's node data is loaded once into LDS (the dissipated vector over a
+// two-node ring, the other face inputs over a one-node ring); the xi and eta faces of the
+// plane are computed from LDS, the zeta face from the column's previous-plane values kept
+// in registers. For every face an updated node uses, the tangential differences are
+// centred (their nodes never lie on a non-periodic end in a tangential direction), so they
+// are taken straight from the ring.
+// ---------------------------------------------------------------------------------------
+enum { sU = 0, sV, sWv, sT, sMu, sMut, sS0, sJinv = sS0 + 9, sDz, sNF = sDz + 4 };
+
+// The inputs of one face from one of its two nodes.
+struct FaceNode {
+  double W[5];   // dissipated vector (rho, rho u, rho v, rho w, e + p)
+  double p, u, v, w, T, mu, mut, lb, nu, jinv;
+  double S[9];
+  double dt[2][4];  // centred differences of (u, v, w, T) along the two tangential directions
+};
+
+// Face flux from the values at its two nodes A, B (B = A + e_d) and the dissipated vector
+// one node beyond each (Wm = W(A - e_d), Wp = W(B + e_d)); m is A's index along d of n.
+template <int d>
+__device__ __forceinline__ void face_core(const FaceNode& a, const FaceNode& b, const double* Wm,
+                                          const double* Wp, int m, int n, bool per,
+                                          const Phys& Ph, double* H) {
+  double FA[5], FB[5];
+  {
+    double un = a.S[3 * d] * a.u + a.S[3 * d + 1] * a.v + a.S[3 * d + 2] * a.w;
+    FA[0] = a.W[0] * un;
+    FA[1] = a.W[1] * un + a.p * a.S[3 * d];
+    FA[2] = a.W[2] * un + a.p * a.S[3 * d + 1];
+    FA[3] = a.W[3] * un + a.p * a.S[3 * d + 2];
+    FA[4] = a.W[4] * un;
+  }
+  {
+    double un = b.S[3 * d] * b.u + b.S[3 * d + 1] * b.v + b.S[3 * d + 2] * b.w;
+    FB[0] = b.W[0] * un;
+    FB[1] = b.W[1] * un + b.p * b.S[3 * d];
+    FB[2] = b.W[2] * un + b.p * b.S[3 * d + 1];
+    FB[3] = b.W[3] * un + b.p * b.S[3 * d + 2];
+    FB[4] = b.W[4] * un;
+  }
+  double dW[5], d3W[5];
+#pragma unroll
+  for (int c = 0; c < 5; ++c) dW[c] = b.W[c] - a.W[c];
+  if (per || (m > 0 && m < n - 2)) {
+#pragma unroll
+    for (int c = 0; c < 5; ++c) d3W[c] = Wp[c] - 3.0 * b.W[c] + 3.0 * a.W[c] - Wm[c];
+  } else if (m == 0) {
+#pragma unroll
+    for (int c = 0; c < 5; ++c) d3W[c] = (Wp[c] - b.W[c]) - 3.0 * dW[c];
+  } else {
+#pragma unroll
+    for (int c = 0; c < 5; ++c) d3W[c] = -3.0 * dW[c] + (a.W[c] - Wm[c]);
+  }
+  double Dd[5];
+  dissipation(0.5 * (a.lb + b.lb), a.nu, b.nu, dW, d3W, Ph, Dd);
+  double Sf[9];
+#pragma unroll
+  for (int c = 0; c < 9; ++c) Sf[c] = 0.5 * (a.S[c] + b.S[c]);
+  const double jf = 0.5 * (a.jinv + b.jinv);
+  double gxi[4][3];
+  gxi[0][d] = b.u - a.u;
+  gxi[1][d] = b.v - a.v;
+  gxi[2][d] = b.w - a.w;
+  gxi[3][d] = b.T - a.T;
+  constexpr int e1 = d == 0 ? 1 : 0, e2 = d == 2 ? 1 : 2;
+#pragma unroll
+  for (int v = 0; v < 4; ++v) {
+    gxi[v][e1] = 0.5 * (a.dt[0][v] + b.dt[0][v]);
+    gxi[v][e2] = 0.5 * (a.dt[1][v] + b.dt[1][v]);
+  }
+  const double muf = 0.5 * (a.mu + b.mu);
+  const double mutf = 0.5 * (a.mut + b.mut);
+  const double ub[3] = {0.5 * (a.u + b.u), 0.5 * (a.v + b.v), 0.5 * (a.w + b.w)};
+  double Fv[5];
+  viscous_flux(Sf, jf, gxi, muf, mutf, ub, d, Ph, Fv);
+  Fv[0] = 0.0;
+#pragma unroll
+  for (int c = 0; c < 5; ++c) H[c] = 0.5 * (FA[c] + FB[c]) - Dd[c] - Fv[c];
+}
+
+template <int TX, int TY>
+struct PlaneLds {
+  static constexpr int RX2 = TX + 4, RY2 = TY + 4, RX1 = TX + 2, RY1 = TY + 2;
+  static constexpr int NW = RX2 * RY2, N1 = RX1 * RY1;
+  static constexpr int NX = (TX + 1) * TY, NY = TX * (TY + 1);
+  // Staging of one plane. Once its faces are computed the same space holds the face
+  // fluxes (xi then eta), 5 * (NX + NY) doubles.
+  union {
+    struct {
+      double W[6][NW];    // W0..W4 and p over the two-node ring
+      double F[sNF][N1];  // other face inputs over the one-node ring
+    } in;
+    double H[5][NX + NY];
+  };
+};
+
+// Fill a FaceNode from LDS at ring-1 position (x, y) of node offset o; the scaled spectral
+// radius and sensor along d come from the node records. Tangential differences are along
+// the two directions other than d, in increasing direction order (zeta's is staged).
+template <int TX, int TY, int d>
+__device__ __forceinline__ void lds_node(const PlaneLds<TX, TY>& L, int x, int y, unsigned o,
+                                         const double* __restrict__ rec, int N, FaceNode& f) {
+  using PL = PlaneLds<TX, TY>;
+  const int p1 = x + PL::RX1 * y;
+  const int p2 = (x + 1) + PL::RX2 * (y + 1);
+#pragma unroll
+  for (int c = 0; c < 5; ++c) f.W[c] = L.in.W[c][p2];
+  f.p = L.in.W[5][p2];
+  f.u = L.in.F[sU][p1];
+  f.v = L.in.F[sV][p1];
+  f.w = L.in.F[sWv][p1];
+  f.T = L.in.F[sT][p1];
+  f.mu = L.in.F[sMu][p1];
+  f.mut = L.in.F[sMut][p1];
+  f.lb = rec[(kRecLb + d) * N + o];
+  f.nu = rec[(kRecNu + d) * N + o];
+#pragma unroll
+  for (int c = 0; c < 9; ++c) f.S[c] = L.in.F[sS0 + c][p1];
+  f.jinv = L.in.F[sJinv][p1];
+  int slot = 0;
+  if (d != 0) {  // centred xi difference
+#pragma unroll
+    for (int v = 0; v < 4; ++v)
+      f.dt[slot][v] = 0.5 * (L.in.F[sU + v][p1 + 1] - L.in.F[sU + v][p1 - 1]);
+    ++slot;
+  }
+  if (d != 1) {  // centred eta difference
+#pragma unroll
+    for (int v = 0; v < 4; ++v)
+      f.dt[slot][v] = 0.5 * (L.in.F[sU + v][p1 + PL::RX1] - L.in.F[sU + v][p1 - PL::RX1]);
+    ++slot;
+  }
+  if (d != 2) {  // zeta difference, staged
+#pragma unroll
+    for (int v = 0; v < 4; ++v) f.dt[slot][v] = L.in.F[sDz + v][p1];
+  }
+}
+
+// Face inputs of node (i, j, k) read straight from global memory, with centred xi and eta
+// differences (for the zeta face's upper node).
+__device__ __forceinline__ void global_node_z(const StageArgs& A, int i, int j, int k,
+                                              FaceNode& f) {
+  const Dims& D = A.D;
+  const int N = (int)D.N;
+  const int ni = D.n[0], nj = D.n[1];
+  const unsigned o = (unsigned)(i + ni * (j + nj * k));
+  const double* __restrict__ q = A.q;
+  const double* __restrict__ rec = A.rec;
+#pragma unroll
+  for (int c = 0; c < 5; ++c) f.W[c] = q[c * N + o];
+  f.p = rec[kRecP * N + o];
+  f.W[4] += f.p;
+  f.u = rec[kRecU * N + o];
+  f.v = rec[kRecV * N + o];
+  f.w = rec[kRecW * N + o];
+  f.T = rec[kRecT * N + o];
+  f.mu = rec[kRecMu * N + o];
+  f.mut = rec[kRecMut * N + o];
+  f.lb = rec[(kRecLb + 2) * N + o];
+  f.nu = rec[(kRecNu + 2) * N + o];
+#pragma unroll
+  for (int c = 0; c < 9; ++c) f.S[c] = A.S[c * N + o];
+  f.jinv = A.jinv[o];
+  const unsigned ip = i + 1 == ni ? o - (unsigned)(ni - 1) : o + 1;
+  const unsigned im = i == 0 ? o + (unsigned)(ni - 1) : o - 1;
+  const unsigned jp = j + 1 == nj ? o - (unsigned)((nj - 1) * ni) : o + ni;
+  const unsigned jm = j == 0 ? o + (unsigned)((nj - 1) * ni) : o - ni;
+#pragma unroll
+  for (int v = 0; v < 4; ++v) {
+    f.dt[0][v] = 0.5 * (rec[(kRecU + v) * N + ip] - rec[(kRecU + v) * N + im]);
+    f.dt[1][v] = 0.5 * (rec[(kRecU + v) * N + jp] - rec[(kRecU + v) * N + jm]);
+  }
+}
+
+// One block per TX x TY column tile marches a chunk of z-planes (z is periodic).
+template <int TX, int TY, int WPE>
+__global__ void __launch_bounds__(TX * TY) __attribute__((amdgpu_waves_per_eu(WPE, 8)))
+k_stage_planes(StageArgs A, int kchunk) {
+  using PL = PlaneLds<TX, TY>;
+  constexpr int NT = TX * TY;
+  constexpr int MW = (PL::NW + NT - 1) / NT;  // staging slots per thread
+  constexpr int M1 = (PL::N1 + NT - 1) / NT;
+  constexpr int MX = (PL::NX + NT - 1) / NT;  // face slots per thread
+  constexpr int MY = (PL::NY + NT - 1) / NT;
+  __shared__ PL L;
+  const Dims& D = A.D;
+  const Phys& Ph = A.P;
+  const int N = (int)D.N;
+  const int ni = D.n[0], nj = D.n[1], nk = D.n[2];
+  const int gx = gridDim.x, gy = gridDim.y;
+  const int lin = blockIdx.x + gx * (blockIdx.y + gy * blockIdx.z);
+  const int t = xcd_tile(lin, gx * gy * gridDim.z);
+  const int bx = t % gx, by = (t / gx) % gy, bz = t / (gx * gy);
+  const int i0 = bx * TX, j0 = by * TY;
+  const int kbeg = bz * kchunk;
+  const int kend = min(kbeg + kchunk, nk);
+  const int tid = threadIdx.x;
+  const int a = tid % TX, b = tid / TX;
+  const int i = i0 + a, j = j0 + b;
+  const bool mine = i < ni && j < nj;
+  const double* __restrict__ q = A.q;
+  const double* __restrict__ rec = A.rec;
+  const double* __restrict__ S = A.S;
+  const unsigned pl = (unsigned)(ni * nj);
+
+  // Zeta face below the chunk, and the dissipated vector one plane below the current one.
+  double hz_lo[5] = {0, 0, 0, 0, 0};
+  double Wlow[5] = {0, 0, 0, 0, 0};
+  if (mine) {
+    const int kl = kbeg == 0 ? nk - 1 : kbeg - 1;
+    face_flux<2>(A, i, j, kl, hz_lo);
+    const unsigned o = (unsigned)(i + ni * (j + nj * kl));
+#pragma unroll
+    for (int c = 0; c < 5; ++c) Wlow[c] = q[c * N + o];
+    Wlow[4] += rec[kRecP * N + o];
+  }
+
+  for (int k = kbeg; k < kend; ++k) {
+    // Every staging load of the plane in flight at once.
+    double vw[MW][6];
+    double vf[M1][sNF];
+#pragma unroll
+    for (int r = 0; r < MW; ++r) {
+      const int s = tid + r * NT;
+      const int ia = wrap_or_out(i0 - 2 + s % PL::RX2, ni, D.per[0]);
+      const int ja = wrap_or_out(j0 - 2 + s / PL::RX2, nj, D.per[1]);
+#pragma unroll
+      for (int c = 0; c < 6; ++c) vw[r][c] = 0.0;
+      if (s < PL::NW && ia >= 0 && ja >= 0) {
+        const unsigned o = (unsigned)(ia + ni * (ja + nj * k));
+#pragma unroll
+        for (int c = 0; c < 5; ++c) vw[r][c] = q[c * N + o];
+        vw[r][5] = rec[kRecP * N + o];
+      }
+    }
+#pragma unroll
+    for (int r = 0; r < M1; ++r) {
+      const int s = tid + r * NT;
+      const int ia = wrap_or_out(i0 - 1 + s % PL::RX1, ni, D.per[0]);
+      const int ja = wrap_or_out(j0 - 1 + s / PL::RX1, nj, D.per[1]);
+#pragma unroll
+      for (int c = 0; c < sNF; ++c) vf[r][c] = 0.0;
+      if (s < PL::N1 && ia >= 0 && ja >= 0) {
+        const unsigned o = (unsigned)(ia + ni * (ja + nj * k));
+        vf[r][sU] = rec[kRecU * N + o];
+        vf[r][sV] = rec[kRecV * N + o];
+        vf[r][sWv] = rec[kRecW * N + o];
+        vf[r][sT] = rec[kRecT * N + o];
+        vf[r][sMu] = rec[kRecMu * N + o];
+        vf[r][sMut] = rec[kRecMut * N + o];
+#pragma unroll
+        for (int c = 0; c < 9; ++c) vf[r][sS0 + c] = S[c * N + o];
+        vf[r][sJinv] = A.jinv[o];
+        const unsigned op = k + 1 == nk ? o - (unsigned)(nk - 1) * pl : o + pl;
+        const unsigned om = k == 0 ? o + (unsigned)(nk - 1) * pl : o - pl;
+#pragma unroll
+        for (int c = 0; c < 4; ++c)
+          vf[r][sDz + c] = 0.5 * (rec[(kRecU + c) * N + op] - rec[(kRecU + c) * N + om]);
+      }
+    }
+    __syncthreads();  // the previous plane's face fluxes have been consumed
+#pragma unroll
+    for (int r = 0; r < MW; ++r) {
+      const int s = tid + r * NT;
+      if (s < PL::NW) {
+#pragma unroll
+        for (int c = 0; c < 4; ++c) L.in.W[c][s] = vw[r][c];
+        L.in.W[4][s] = vw[r][4] + vw[r][5];
+        L.in.W[5][s] = vw[r][5];
+      }
+    }
+#pragma unroll
+    for (int r = 0; r < M1; ++r) {
+      const int s = tid + r * NT;
+      if (s < PL::N1)
+#pragma unroll
+        for (int c = 0; c < sNF; ++c) L.in.F[c][s] = vf[r][c];
+    }
+    __syncthreads();
+
+    // Faces of the plane, held in registers until the staging space is free.
+    double hx[MX][5], hy[MY][5];
+#pragma unroll
+    for (int r = 0; r < MX; ++r) {
+      const int s = tid + r * NT;
+#pragma unroll
+      for (int c = 0; c < 5; ++c) hx[r][c] = 0.0;
+      const int fx = s % (TX + 1), fy = s / (TX + 1);
+      const int ia = wrap_or_out(i0 - 1 + fx, ni, D.per[0]);
+      const int ja = wrap_or_out(j0 + fy, nj, D.per[1]);
+      if (s < PL::NX && ia >= 0 && ja >= 0 && (D.per[0] || ia < ni - 1)) {
+        const unsigned oa = (unsigned)(ia + ni * (ja + nj * k));
+        const unsigned ob = ia + 1 == ni ? oa - (unsigned)(ni - 1) : oa + 1;
+        FaceNode na, nb;
+        lds_node<TX, TY, 0>(L, fx, fy + 1, oa, rec, N, na);
+        lds_node<TX, TY, 0>(L, fx + 1, fy + 1, ob, rec, N, nb);
+        double wm[5], wp[5];
+#pragma unroll
+        for (int c = 0; c < 5; ++c) {
+          wm[c] = L.in.W[c][fx + PL::RX2 * (fy + 2)];
+          wp[c] = L.in.W[c][fx + 3 + PL::RX2 * (fy + 2)];
+        }
+        face_core<0>(na, nb, wm, wp, ia, ni, D.per[0], Ph, hx[r]);
+      }
+    }
+#pragma unroll
+    for (int r = 0; r < MY; ++r) {
+      const int s = tid + r * NT;
+#pragma unroll
+      for (int c = 0; c < 5; ++c) hy[r][c] = 0.0;
+      const int fx = s % TX, fy = s / TX;
+      const int ia = wrap_or_out(i0 + fx, ni, D.per[0]);
+      const int ja = wrap_or_out(j0 - 1 + fy, nj, D.per[1]);
+      if (s < PL::NY && ia >= 0 && ja >= 0 && (D.per[1] || ja < nj - 1)) {
+        const unsigned oa = (unsigned)(ia + ni * (ja + nj * k));
+        const unsigned ob = ja + 1 == nj ? oa - (unsigned)((nj - 1) * ni) : oa + ni;
+        FaceNode na, nb;
+        lds_node<TX, TY, 1>(L, fx + 1, fy, oa, rec, N, na);
+        lds_node<TX, TY, 1>(L, fx + 1, fy + 1, ob, rec, N, nb);
+        double wm[5], wp[5];
+#pragma unroll
+        for (int c = 0; c < 5; ++c) {
+          wm[c] = L.in.W[c][fx + 2 + PL::RX2 * fy];
+          wp[c] = L.in.W[c][fx + 2 + PL::RX2 * (fy + 3)];
+        }
+        face_core<1>(na, nb, wm, wp, ja, nj, D.per[1], Ph, hy[r]);
+      }
+    }
+    // Zeta face above the own node: lower node from LDS, upper node from global memory.
+    double hz[5] = {0, 0, 0, 0, 0};
+    double Wcur[5] = {0, 0, 0, 0, 0};
+    if (mine) {
+      const unsigned o = (unsigned)(i + ni * (j + nj * k));
+      FaceNode na, nb;
+      lds_node<TX, TY, 2>(L, a + 1, b + 1, o, rec, N, na);
+      const int kp = k + 1 == nk ? 0 : k + 1;
+      const int kp2 = kp + 1 == nk ? 0 : kp + 1;
+      global_node_z(A, i, j, kp, nb);
+      const unsigned o2 = (unsigned)(i + ni * (j + nj * kp2));
+      double wp[5];
+#pragma unroll
+      for (int c = 0; c < 5; ++c) wp[c] = q[c * N + o2];
+      wp[4] += rec[kRecP * N + o2];
+      face_core<2>(na, nb, Wlow, wp, k, nk, true, Ph, hz);
+#pragma unroll
+      for (int c = 0; c < 5; ++c) Wcur[c] = na.W[c];
+    }
+    __syncthreads();  // staging reads done: the space now takes the face fluxes
+#pragma unroll
+    for (int r = 0; r < MX; ++r) {
+      const int s = tid + r * NT;
+      if (s < PL::NX)
+#pragma unroll
+        for (int c = 0; c < 5; ++c) L.H[c][s] = hx[r][c];
+    }
+#pragma unroll
+    for (int r = 0; r < MY; ++r) {
+      const int s = tid + r * NT;
+      if (s < PL::NY)
+#pragma unroll
+        for (int c = 0; c < 5; ++c) L.H[c][PL::NX + s] = hy[r][c];
+    }
+    __syncthreads();
+    if (mine) {
+      const int o = i + ni * (j + nj * k);
+      if (is_updated(D, i, j, k)) {
+        const int sx = a + (TX + 1) * b, sy = PL::NX + a + TX * b;
+        double fac = 0.0;
+        if (A.mode == 1) fac = A.alpha * A.dt[0] * A.jac[o];
+#pragma unroll
+        for (int c = 0; c < 5; ++c) {
+          double rr = 0.0;
+          rr += L.H[c][sx + 1] - L.H[c][sx];
+          rr += L.H[c][sy + TX] - L.H[c][sy];
+          rr += hz[c] - hz_lo[c];
+          if (A.mode == 0)
+            A.out[c * N + o] = rr;
+          else
+            A.out[c * N + o] = A.q0[c * N + o] - fac * rr;
+        }
+      } else if (A.mode == 0) {
+#pragma unroll
+        for (int c = 0; c < 5; ++c) A.out[c * N + o] = 0.0;
+      }
+#pragma unroll
+      for (int c = 0; c < 5; ++c) {
+        hz_lo[c] = hz[c];
+        Wlow[c] = Wcur[c];
+      }
+    }
+  }
+}
+
 template <int TX, int TY, int WPE = 2>
 hipError_t launch_tile(const StageArgs& A, hipStream_t s, int kmin) {
   const int gx = (A.D.n[0] + TX - 1) / TX, gy = (A.D.n[1] + TY - 1) / TY;
@@ -404,10 +799,33 @@ hipError_t launch_nodes(const StageArgs& A, hipStream_t s) {
 
 const char* const kTileNames[kNumTiles] = {"32x8", "64x4", "16x16", "32x4", "64x2",
                                            "128x2", "32x8/w3", "64x4/w3", "32x8/w4",
-                                           "64x4/w4"};
+                                           "64x4/w4", "planes32x4", "planes16x8",
+                                           "planes16x16", "planes32x8", "planes16x8/w2",
+                                           "planes16x16/w2"};
+
+template <int TX, int TY, int WPE = 1>
+hipError_t launch_planes(const StageArgs& A, hipStream_t s, int kmin) {
+  const int gx = (A.D.n[0] + TX - 1) / TX, gy = (A.D.n[1] + TY - 1) / TY;
+  int nz = (1024 + gx * gy - 1) / (gx * gy);
+  nz = max(1, min(nz, A.D.n[2] / kmin));
+  const int kchunk = (A.D.n[2] + nz - 1) / nz;
+  nz = (A.D.n[2] + kchunk - 1) / kchunk;
+  hipLaunchKernelGGL((k_stage_planes<TX, TY, WPE>), dim3(gx, gy, nz), dim3(TX * TY), 0, s, A, kchunk);
+  return hipGetLastError();
+}
 
 hipError_t launch_stage(const StageArgs& A, hipStream_t s) {
   const int kmin = A.kmin > 0 ? A.kmin : 8;
+  // The plane-staged kernel needs a periodic z direction (true of every supported set).
+  if (A.D.per[2]) switch (A.tile) {
+      case 10: return launch_planes<32, 4>(A, s, kmin);
+      case 11: return launch_planes<16, 8>(A, s, kmin);
+      case 12: return launch_planes<16, 16>(A, s, kmin);
+      case 13: return launch_planes<32, 8>(A, s, kmin);
+      case 14: return launch_planes<16, 8, 2>(A, s, kmin);
+      case 15: return launch_planes<16, 16, 2>(A, s, kmin);
+      default: break;
+    }
   switch (A.tile) {
     case 1: return launch_tile<64, 4>(A, s, kmin);
     case 2: return launch_tile<16, 16>(A, s, kmin);
