@@ -60,8 +60,11 @@ struct les_ctx {
   double* qa = nullptr;
   double* qb = nullptr;
 
-  // Node records of the stage kernels [kRecCount][N].
+  // Node records of the stage kernels [kRecCount][N] (FP64 form), or the mixed form's
+  // FP32 records and FP32 copy of the metrics.
   double* rec = nullptr;
+  float* rec32 = nullptr;
+  float* S32 = nullptr;
   // Stage kernel launch shape (index into the tile table) and smallest z-chunk depth.
   int tile = 13;
   int kmin = 8;

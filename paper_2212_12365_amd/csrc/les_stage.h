@@ -24,6 +24,10 @@ struct StageArgs {
   const double* jac;   // 1/J^-1 at updated nodes [N]
   double* rec;         // node records [kRecCount][N]
   double* mut_out;     // optional copy of the eddy viscosity [N] (k_nodes)
+  // Mixed form: FP32 metrics and node records; the fluxes are evaluated in FP32.
+  int mixed;
+  const float* S32;    // [9][N]
+  float* rec32;        // [kRecCount][N]
   // k_stage output: mode 0 -> residual into out; mode 1 -> out = q0 - alpha dt J RHS.
   int mode;
   double* out;

@@ -39,21 +39,40 @@ __device__ __forceinline__ Prim load_prim(const double* __restrict__ q, int N, i
   return prim_from_q(q[o], q[N + o], q[2 * N + o], q[3 * N + o], q[4 * N + o], P);
 }
 
+template <typename R>
+__device__ __forceinline__ const R* metrics_of(const StageArgs& A);
+template <>
+__device__ __forceinline__ const double* metrics_of<double>(const StageArgs& A) { return A.S; }
+template <>
+__device__ __forceinline__ const float* metrics_of<float>(const StageArgs& A) { return A.S32; }
+template <typename R>
+__device__ __forceinline__ R* records_of(const StageArgs& A);
+template <>
+__device__ __forceinline__ double* records_of<double>(const StageArgs& A) { return A.rec; }
+template <>
+__device__ __forceinline__ float* records_of<float>(const StageArgs& A) { return A.rec32; }
+
+// Node record of one node. Primitive variables are formed in FP64 from the FP64 state;
+// the differences, eddy viscosity, spectral radii and sensors are evaluated in R.
+template <typename R>
 __global__ void __launch_bounds__(256) k_nodes(StageArgs A) {
   const Dims& D = A.D;
+  const PhysT<R> P(A.P);
   int i = blockIdx.x * blockDim.x + threadIdx.x;
   int j = blockIdx.y * blockDim.y + threadIdx.y;
   int k = blockIdx.z;
   if (i >= D.n[0] || j >= D.n[1]) return;
   const int N = (int)D.N;
   const double* __restrict__ q = A.q;
+  const R* __restrict__ Sm = metrics_of<R>(A);
   int ix[3] = {i, j, k};
   int o = off3(D, i, j, k);
   Prim s = load_prim(q, N, o, A.P);
+  const R su = (R)s.u, sv = (R)s.v, sw = (R)s.w, sp = (R)s.p;
   // Velocity differences delta_e u_m (centred; one-sided at the ends of a non-periodic
   // direction) and pressure sensors along e.
-  double du[3][3];
-  double nu[3];
+  R du[3][3];
+  R nu[3];
   for (int e = 0; e < 3; ++e) {
     int n = D.n[e], m = ix[e];
     int stride = e == 0 ? 1 : (e == 1 ? D.n[0] : D.n[0] * D.n[1]);
@@ -62,40 +81,41 @@ __global__ void __launch_bounds__(256) k_nodes(StageArgs A) {
       int mp = m + 1 == n ? 0 : m + 1, mm = m == 0 ? n - 1 : m - 1;
       Prim a = load_prim(q, N, o + (mp - m) * stride, A.P);
       Prim b = load_prim(q, N, o + (mm - m) * stride, A.P);
-      du[e][0] = 0.5 * (a.u - b.u);
-      du[e][1] = 0.5 * (a.v - b.v);
-      du[e][2] = 0.5 * (a.w - b.w);
-      nu[e] = sensor(b.p, s.p, a.p);
+      du[e][0] = (R)0.5 * ((R)a.u - (R)b.u);
+      du[e][1] = (R)0.5 * ((R)a.v - (R)b.v);
+      du[e][2] = (R)0.5 * ((R)a.w - (R)b.w);
+      nu[e] = sensor<R>((R)b.p, sp, (R)a.p);
     } else {
       int sg = m == 0 ? 1 : -1;  // towards the interior
       Prim a = load_prim(q, N, o + sg * stride, A.P);
       Prim b = load_prim(q, N, o + 2 * sg * stride, A.P);
-      double h = 0.5 * sg;
-      du[e][0] = h * (-3.0 * s.u + 4.0 * a.u - b.u);
-      du[e][1] = h * (-3.0 * s.v + 4.0 * a.v - b.v);
-      du[e][2] = h * (-3.0 * s.w + 4.0 * a.w - b.w);
+      R h = (R)0.5 * (R)sg;
+      du[e][0] = h * ((R)-3 * su + (R)4 * (R)a.u - (R)b.u);
+      du[e][1] = h * ((R)-3 * sv + (R)4 * (R)a.v - (R)b.v);
+      du[e][2] = h * ((R)-3 * sw + (R)4 * (R)a.w - (R)b.w);
       // The boundary node takes the sensor of its interior neighbour c (p at c-1, c, c+1).
-      nu[e] = m == 0 ? sensor(s.p, a.p, b.p) : sensor(b.p, a.p, s.p);
+      nu[e] = m == 0 ? sensor<R>(sp, (R)a.p, (R)b.p) : sensor<R>((R)b.p, (R)a.p, sp);
     }
   }
-  double sm[9];
+  R sm[9];
 #pragma unroll
-  for (int c = 0; c < 9; ++c) sm[c] = A.S[c * N + o];
-  double jinv = A.jinv[o];
-  double mut = smagorinsky(sm, du, s.rho, jinv, A.P);
-  double a = sqrt(s.T);
-  double l0 = spectral(sm[0], sm[1], sm[2], s.u, s.v, s.w, a);
-  double l1 = spectral(sm[3], sm[4], sm[5], s.u, s.v, s.w, a);
-  double l2 = spectral(sm[6], sm[7], sm[8], s.u, s.v, s.w, a);
-  double lb[3];
-  scaled_radii(l0, l1, l2, lb);
-  double* __restrict__ r = A.rec;
-  r[kRecU * N + o] = s.u;
-  r[kRecV * N + o] = s.v;
-  r[kRecW * N + o] = s.w;
-  r[kRecT * N + o] = s.T;
-  r[kRecP * N + o] = s.p;
-  r[kRecMu * N + o] = sutherland(s.T, A.P);
+  for (int c = 0; c < 9; ++c) sm[c] = Sm[c * N + o];
+  const R jinv = (R)A.jinv[o];
+  const R T = (R)s.T;
+  const R mut = smagorinsky<R>(sm, du, (R)s.rho, jinv, P);
+  const R a = sqrt(T);
+  const R l0 = spectral<R>(sm[0], sm[1], sm[2], su, sv, sw, a);
+  const R l1 = spectral<R>(sm[3], sm[4], sm[5], su, sv, sw, a);
+  const R l2 = spectral<R>(sm[6], sm[7], sm[8], su, sv, sw, a);
+  R lb[3];
+  scaled_radii<R>(l0, l1, l2, lb);
+  R* __restrict__ r = records_of<R>(A);
+  r[kRecU * N + o] = su;
+  r[kRecV * N + o] = sv;
+  r[kRecW * N + o] = sw;
+  r[kRecT * N + o] = T;
+  r[kRecP * N + o] = (R)(s.p - A.P.p_ref);
+  r[kRecMu * N + o] = sutherland<R>(T, P);
   r[kRecMut * N + o] = mut;
   r[(kRecLb + 0) * N + o] = lb[0];
   r[(kRecLb + 1) * N + o] = lb[1];
@@ -103,7 +123,7 @@ __global__ void __launch_bounds__(256) k_nodes(StageArgs A) {
   r[(kRecNu + 0) * N + o] = nu[0];
   r[(kRecNu + 1) * N + o] = nu[1];
   r[(kRecNu + 2) * N + o] = nu[2];
-  if (A.mut_out) A.mut_out[o] = mut;
+  if (A.mut_out) A.mut_out[o] = (double)mut;
 }
 
 // ---------------------------------------------------------------------------------------
@@ -392,78 +412,7 @@ k_stage(StageArgs A, int kchunk) {
 // ---------------------------------------------------------------------------------------
 enum { sU = 0, sV, sWv, sT, sMu, sMut, sS0, sJinv = sS0 + 9, sDz, sNF = sDz + 4 };
 
-// The inputs of one face from one of its two nodes.
-struct FaceNode {
-  double W[5];   // dissipated vector (rho, rho u, rho v, rho w, e + p)
-  double p, u, v, w, T, mu, mut, lb, nu, jinv;
-  double S[9];
-  double dt[2][4];  // centred differences of (u, v, w, T) along the two tangential directions
-};
-
-// Face flux from the values at its two nodes A, B (B = A + e_d) and the dissipated vector
-// one node beyond each (Wm = W(A - e_d), Wp = W(B + e_d)); m is A's index along d of n.
-template <int d>
-__device__ __forceinline__ void face_core(const FaceNode& a, const FaceNode& b, const double* Wm,
-                                          const double* Wp, int m, int n, bool per,
-                                          const Phys& Ph, double* H) {
-  double FA[5], FB[5];
-  {
-    double un = a.S[3 * d] * a.u + a.S[3 * d + 1] * a.v + a.S[3 * d + 2] * a.w;
-    FA[0] = a.W[0] * un;
-    FA[1] = a.W[1] * un + a.p * a.S[3 * d];
-    FA[2] = a.W[2] * un + a.p * a.S[3 * d + 1];
-    FA[3] = a.W[3] * un + a.p * a.S[3 * d + 2];
-    FA[4] = a.W[4] * un;
-  }
-  {
-    double un = b.S[3 * d] * b.u + b.S[3 * d + 1] * b.v + b.S[3 * d + 2] * b.w;
-    FB[0] = b.W[0] * un;
-    FB[1] = b.W[1] * un + b.p * b.S[3 * d];
-    FB[2] = b.W[2] * un + b.p * b.S[3 * d + 1];
-    FB[3] = b.W[3] * un + b.p * b.S[3 * d + 2];
-    FB[4] = b.W[4] * un;
-  }
-  double dW[5], d3W[5];
-#pragma unroll
-  for (int c = 0; c < 5; ++c) dW[c] = b.W[c] - a.W[c];
-  if (per || (m > 0 && m < n - 2)) {
-#pragma unroll
-    for (int c = 0; c < 5; ++c) d3W[c] = Wp[c] - 3.0 * b.W[c] + 3.0 * a.W[c] - Wm[c];
-  } else if (m == 0) {
-#pragma unroll
-    for (int c = 0; c < 5; ++c) d3W[c] = (Wp[c] - b.W[c]) - 3.0 * dW[c];
-  } else {
-#pragma unroll
-    for (int c = 0; c < 5; ++c) d3W[c] = -3.0 * dW[c] + (a.W[c] - Wm[c]);
-  }
-  double Dd[5];
-  dissipation(0.5 * (a.lb + b.lb), a.nu, b.nu, dW, d3W, Ph, Dd);
-  double Sf[9];
-#pragma unroll
-  for (int c = 0; c < 9; ++c) Sf[c] = 0.5 * (a.S[c] + b.S[c]);
-  const double jf = 0.5 * (a.jinv + b.jinv);
-  double gxi[4][3];
-  gxi[0][d] = b.u - a.u;
-  gxi[1][d] = b.v - a.v;
-  gxi[2][d] = b.w - a.w;
-  gxi[3][d] = b.T - a.T;
-  constexpr int e1 = d == 0 ? 1 : 0, e2 = d == 2 ? 1 : 2;
-#pragma unroll
-  for (int v = 0; v < 4; ++v) {
-    gxi[v][e1] = 0.5 * (a.dt[0][v] + b.dt[0][v]);
-    gxi[v][e2] = 0.5 * (a.dt[1][v] + b.dt[1][v]);
-  }
-  const double muf = 0.5 * (a.mu + b.mu);
-  const double mutf = 0.5 * (a.mut + b.mut);
-  const double ub[3] = {0.5 * (a.u + b.u), 0.5 * (a.v + b.v), 0.5 * (a.w + b.w)};
-  double Fv[5];
-  viscous_flux(Sf, jf, gxi, muf, mutf, ub, d, Ph, Fv);
-  Fv[0] = 0.0;
-#pragma unroll
-  for (int c = 0; c < 5; ++c) H[c] = 0.5 * (FA[c] + FB[c]) - Dd[c] - Fv[c];
-}
-
-template <int TX, int TY>
+template <int TX, int TY, typename R>
 struct PlaneLds {
   static constexpr int RX2 = TX + 4, RY2 = TY + 4, RX1 = TX + 2, RY1 = TY + 2;
   static constexpr int NW = RX2 * RY2, N1 = RX1 * RY1;
@@ -472,96 +421,146 @@ struct PlaneLds {
   // fluxes (xi then eta), 5 * (NX + NY) doubles.
   union {
     struct {
-      double W[6][NW];    // W0..W4 and p over the two-node ring
-      double F[sNF][N1];  // other face inputs over the one-node ring
+      R W[6][NW];    // W0..W4 and p over the two-node ring
+      R F[sNF][N1];  // other face inputs over the one-node ring
     } in;
-    double H[5][NX + NY];
+    R H[5][NX + NY];
   };
 };
 
-// Fill a FaceNode from LDS at ring-1 position (x, y) of node offset o; the scaled spectral
-// radius and sensor along d come from the node records. Tangential differences are along
-// the two directions other than d, in increasing direction order (zeta's is staged).
-template <int TX, int TY, int d>
-__device__ __forceinline__ void lds_node(const PlaneLds<TX, TY>& L, int x, int y, unsigned o,
-                                         const double* __restrict__ rec, int N, FaceNode& f) {
-  using PL = PlaneLds<TX, TY>;
-  const int p1 = x + PL::RX1 * y;
-  const int p2 = (x + 1) + PL::RX2 * (y + 1);
-#pragma unroll
-  for (int c = 0; c < 5; ++c) f.W[c] = L.in.W[c][p2];
-  f.p = L.in.W[5][p2];
-  f.u = L.in.F[sU][p1];
-  f.v = L.in.F[sV][p1];
-  f.w = L.in.F[sWv][p1];
-  f.T = L.in.F[sT][p1];
-  f.mu = L.in.F[sMu][p1];
-  f.mut = L.in.F[sMut][p1];
-  f.lb = rec[(kRecLb + d) * N + o];
-  f.nu = rec[(kRecNu + d) * N + o];
-#pragma unroll
-  for (int c = 0; c < 9; ++c) f.S[c] = L.in.F[sS0 + c][p1];
-  f.jinv = L.in.F[sJinv][p1];
-  int slot = 0;
-  if (d != 0) {  // centred xi difference
-#pragma unroll
-    for (int v = 0; v < 4; ++v)
-      f.dt[slot][v] = 0.5 * (L.in.F[sU + v][p1 + 1] - L.in.F[sU + v][p1 - 1]);
-    ++slot;
+// Face inputs of a node staged in LDS, read at the point of use. Tangential differences
+// are centred in-plane and staged along zeta; lb/nu along d come from the node records.
+template <int TX, int TY, int d, typename R>
+struct LdsNode {
+  using PL = PlaneLds<TX, TY, R>;
+  const PL& L;
+  int p1, p2;
+  unsigned o;
+  const R* __restrict__ rec;
+  int N;
+  __device__ R W(int c) const { return L.in.W[c][p2]; }
+  __device__ R p() const { return L.in.W[5][p2]; }
+  __device__ R f(int v) const { return L.in.F[sU + v][p1]; }  // u, v, w, T
+  __device__ R mu() const { return L.in.F[sMu][p1]; }
+  __device__ R mut() const { return L.in.F[sMut][p1]; }
+  __device__ R S(int c) const { return L.in.F[sS0 + c][p1]; }
+  __device__ R jinv() const { return L.in.F[sJinv][p1]; }
+  __device__ R lb() const { return rec[(kRecLb + d) * N + o]; }
+  __device__ R nu() const { return rec[(kRecNu + d) * N + o]; }
+  // Difference along the e-th tangential direction (in increasing direction order).
+  __device__ R dt(int e, int v) const {
+    const int dir = e == 0 ? (d == 0 ? 1 : 0) : (d == 2 ? 1 : 2);
+    if (dir == 0) return (R)0.5 * (L.in.F[sU + v][p1 + 1] - L.in.F[sU + v][p1 - 1]);
+    if (dir == 1) return (R)0.5 * (L.in.F[sU + v][p1 + PL::RX1] - L.in.F[sU + v][p1 - PL::RX1]);
+    return L.in.F[sDz + v][p1];
   }
-  if (d != 1) {  // centred eta difference
-#pragma unroll
-    for (int v = 0; v < 4; ++v)
-      f.dt[slot][v] = 0.5 * (L.in.F[sU + v][p1 + PL::RX1] - L.in.F[sU + v][p1 - PL::RX1]);
-    ++slot;
+};
+
+// Face inputs of node (i, j, k) from global memory (zeta faces), with centred xi and eta
+// differences.
+template <typename R>
+struct GlobalNodeZ {
+  const StageArgs& A;
+  unsigned o, ip, im, jp, jm;
+  int N;
+  const R* __restrict__ rec;
+  const R* __restrict__ Sm;
+  __device__ GlobalNodeZ(const StageArgs& A_, int i, int j, int k)
+      : A(A_), N((int)A_.D.N), rec(records_of<R>(A_)), Sm(metrics_of<R>(A_)) {
+    const int ni = A.D.n[0], nj = A.D.n[1];
+    o = (unsigned)(i + ni * (j + nj * k));
+    ip = i + 1 == ni ? o - (unsigned)(ni - 1) : o + 1;
+    im = i == 0 ? o + (unsigned)(ni - 1) : o - 1;
+    jp = j + 1 == nj ? o - (unsigned)((nj - 1) * ni) : o + ni;
+    jm = j == 0 ? o + (unsigned)((nj - 1) * ni) : o - ni;
   }
-  if (d != 2) {  // zeta difference, staged
+  __device__ R p() const { return rec[kRecP * N + o]; }
+  __device__ R W(int c) const {
+    if (c < 4) return (R)A.q[c * N + o];
+    return (R)(A.q[4 * N + o] + (double)p() + A.P.p_ref);
+  }
+  __device__ R f(int v) const { return rec[(kRecU + v) * N + o]; }
+  __device__ R mu() const { return rec[kRecMu * N + o]; }
+  __device__ R mut() const { return rec[kRecMut * N + o]; }
+  __device__ R S(int c) const { return Sm[c * N + o]; }
+  __device__ R jinv() const { return (R)A.jinv[o]; }
+  __device__ R lb() const { return rec[(kRecLb + 2) * N + o]; }
+  __device__ R nu() const { return rec[(kRecNu + 2) * N + o]; }
+  __device__ R dt(int e, int v) const {
+    if (e == 0) return (R)0.5 * (rec[(kRecU + v) * N + ip] - rec[(kRecU + v) * N + im]);
+    return (R)0.5 * (rec[(kRecU + v) * N + jp] - rec[(kRecU + v) * N + jm]);
+  }
+};
+
+// Total numerical flux H = (F_A + F_B)/2 - D - F_v on a face along d (paper, Spatial
+// Discretization: interface flux with the Turkel-Vatsa terms; viscous flux from the two
+// nodes of the interface), evaluated from node accessors a (A) and b (B = A + e_d) in the
+// order the oracle evaluates it. Wm = W(A - e_d), Wp = W(B + e_d); m is A's index along d.
+template <int d, typename R, typename NA, typename NB>
+__device__ __forceinline__ void face_eval(const NA& a, const NB& b, const R* Wm, const R* Wp,
+                                          int m, int n, bool per, const PhysT<R>& Ph, R* H) {
+  {  // central inviscid part
+    const R una = a.S(3 * d) * a.f(0) + a.S(3 * d + 1) * a.f(1) + a.S(3 * d + 2) * a.f(2);
+    const R unb = b.S(3 * d) * b.f(0) + b.S(3 * d + 1) * b.f(1) + b.S(3 * d + 2) * b.f(2);
+    const R pa = a.p(), pb = b.p();
+    H[0] = (R)0.5 * (a.W(0) * una + b.W(0) * unb);
 #pragma unroll
-    for (int v = 0; v < 4; ++v) f.dt[slot][v] = L.in.F[sDz + v][p1];
+    for (int c = 1; c < 4; ++c)
+      H[c] = (R)0.5 * ((a.W(c) * una + pa * a.S(3 * d + c - 1)) +
+                       (b.W(c) * unb + pb * b.S(3 * d + c - 1)));
+    H[4] = (R)0.5 * (a.W(4) * una + b.W(4) * unb);
+  }
+  {  // artificial dissipation
+    R dW[5], d3W[5];
+#pragma unroll
+    for (int c = 0; c < 5; ++c) dW[c] = b.W(c) - a.W(c);
+    if (per || (m > 0 && m < n - 2)) {
+#pragma unroll
+      for (int c = 0; c < 5; ++c) d3W[c] = Wp[c] - (R)3 * b.W(c) + (R)3 * a.W(c) - Wm[c];
+    } else if (m == 0) {
+#pragma unroll
+      for (int c = 0; c < 5; ++c) d3W[c] = (Wp[c] - b.W(c)) - (R)3 * dW[c];
+    } else {
+#pragma unroll
+      for (int c = 0; c < 5; ++c) d3W[c] = (R)-3 * dW[c] + (a.W(c) - Wm[c]);
+    }
+    R Dd[5];
+    dissipation<R>((R)0.5 * (a.lb() + b.lb()), a.nu(), b.nu(), dW, d3W, Ph, Dd);
+#pragma unroll
+    for (int c = 0; c < 5; ++c) H[c] = H[c] - Dd[c];
+  }
+  {  // viscous and subgrid part
+    R Sf[9];
+#pragma unroll
+    for (int c = 0; c < 9; ++c) Sf[c] = (R)0.5 * (a.S(c) + b.S(c));
+    const R jf = (R)0.5 * (a.jinv() + b.jinv());
+    constexpr int e1 = d == 0 ? 1 : 0, e2 = d == 2 ? 1 : 2;
+    R gxi[4][3];
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      gxi[v][d] = b.f(v) - a.f(v);
+      gxi[v][e1] = (R)0.5 * (a.dt(0, v) + b.dt(0, v));
+      gxi[v][e2] = (R)0.5 * (a.dt(1, v) + b.dt(1, v));
+    }
+    const R muf = (R)0.5 * (a.mu() + b.mu());
+    const R mutf = (R)0.5 * (a.mut() + b.mut());
+    const R ub[3] = {(R)0.5 * (a.f(0) + b.f(0)), (R)0.5 * (a.f(1) + b.f(1)),
+                     (R)0.5 * (a.f(2) + b.f(2))};
+    R Fv[5];
+    viscous_flux<R>(Sf, jf, gxi, muf, mutf, ub, d, Ph, Fv);
+#pragma unroll
+    for (int c = 1; c < 5; ++c) H[c] = H[c] - Fv[c];
+    H[0] = H[0] - (R)0;
   }
 }
 
-// Face inputs of node (i, j, k) read straight from global memory, with centred xi and eta
-// differences (for the zeta face's upper node).
-__device__ __forceinline__ void global_node_z(const StageArgs& A, int i, int j, int k,
-                                              FaceNode& f) {
-  const Dims& D = A.D;
-  const int N = (int)D.N;
-  const int ni = D.n[0], nj = D.n[1];
-  const unsigned o = (unsigned)(i + ni * (j + nj * k));
-  const double* __restrict__ q = A.q;
-  const double* __restrict__ rec = A.rec;
-#pragma unroll
-  for (int c = 0; c < 5; ++c) f.W[c] = q[c * N + o];
-  f.p = rec[kRecP * N + o];
-  f.W[4] += f.p;
-  f.u = rec[kRecU * N + o];
-  f.v = rec[kRecV * N + o];
-  f.w = rec[kRecW * N + o];
-  f.T = rec[kRecT * N + o];
-  f.mu = rec[kRecMu * N + o];
-  f.mut = rec[kRecMut * N + o];
-  f.lb = rec[(kRecLb + 2) * N + o];
-  f.nu = rec[(kRecNu + 2) * N + o];
-#pragma unroll
-  for (int c = 0; c < 9; ++c) f.S[c] = A.S[c * N + o];
-  f.jinv = A.jinv[o];
-  const unsigned ip = i + 1 == ni ? o - (unsigned)(ni - 1) : o + 1;
-  const unsigned im = i == 0 ? o + (unsigned)(ni - 1) : o - 1;
-  const unsigned jp = j + 1 == nj ? o - (unsigned)((nj - 1) * ni) : o + ni;
-  const unsigned jm = j == 0 ? o + (unsigned)((nj - 1) * ni) : o - ni;
-#pragma unroll
-  for (int v = 0; v < 4; ++v) {
-    f.dt[0][v] = 0.5 * (rec[(kRecU + v) * N + ip] - rec[(kRecU + v) * N + im]);
-    f.dt[1][v] = 0.5 * (rec[(kRecU + v) * N + jp] - rec[(kRecU + v) * N + jm]);
-  }
-}
-
-// One block per TX x TY column tile marches a chunk of z-planes (z is periodic).
-template <int TX, int TY, int WPE>
+// One block per TX x TY column tile marches a chunk of z-planes (z is periodic). R is the
+// arithmetic type of the fluxes (double; float in the mixed form, where the state, the
+// Runge-Kutta update, J^-1 and J stay FP64).
+template <int TX, int TY, int WPE, typename R>
 __global__ void __launch_bounds__(TX * TY) __attribute__((amdgpu_waves_per_eu(WPE, 8)))
 k_stage_planes(StageArgs A, int kchunk) {
-  using PL = PlaneLds<TX, TY>;
+  using PL = PlaneLds<TX, TY, R>;
   constexpr int NT = TX * TY;
   constexpr int MW = (PL::NW + NT - 1) / NT;  // staging slots per thread
   constexpr int M1 = (PL::N1 + NT - 1) / NT;
@@ -569,7 +568,7 @@ k_stage_planes(StageArgs A, int kchunk) {
   constexpr int MY = (PL::NY + NT - 1) / NT;
   __shared__ PL L;
   const Dims& D = A.D;
-  const Phys& Ph = A.P;
+  const PhysT<R> Ph(A.P);
   const int N = (int)D.N;
   const int ni = D.n[0], nj = D.n[1], nk = D.n[2];
   const int gx = gridDim.x, gy = gridDim.y;
@@ -584,38 +583,51 @@ k_stage_planes(StageArgs A, int kchunk) {
   const int i = i0 + a, j = j0 + b;
   const bool mine = i < ni && j < nj;
   const double* __restrict__ q = A.q;
-  const double* __restrict__ rec = A.rec;
-  const double* __restrict__ S = A.S;
+  const R* __restrict__ rec = records_of<R>(A);
+  const R* __restrict__ S = metrics_of<R>(A);
   const unsigned pl = (unsigned)(ni * nj);
 
   // Zeta face below the chunk, and the dissipated vector one plane below the current one.
-  double hz_lo[5] = {0, 0, 0, 0, 0};
-  double Wlow[5] = {0, 0, 0, 0, 0};
+  R hz_lo[5] = {0, 0, 0, 0, 0};
+  R Wlow[5] = {0, 0, 0, 0, 0};
   if (mine) {
     const int kl = kbeg == 0 ? nk - 1 : kbeg - 1;
-    face_flux<2>(A, i, j, kl, hz_lo);
-    const unsigned o = (unsigned)(i + ni * (j + nj * kl));
+    const int kl2 = kl == 0 ? nk - 1 : kl - 1;
+    const GlobalNodeZ<R> na(A, i, j, kl), nb(A, i, j, kbeg);
+    const int kp = kbeg + 1 == nk ? 0 : kbeg + 1;
+    const unsigned om = (unsigned)(i + ni * (j + nj * kl2));
+    const unsigned op = (unsigned)(i + ni * (j + nj * kp));
+    R wm[5], wp[5];
 #pragma unroll
-    for (int c = 0; c < 5; ++c) Wlow[c] = q[c * N + o];
-    Wlow[4] += rec[kRecP * N + o];
+    for (int c = 0; c < 4; ++c) {
+      wm[c] = (R)q[c * N + om];
+      wp[c] = (R)q[c * N + op];
+    }
+    wm[4] = (R)(q[4 * N + om] + (double)rec[kRecP * N + om] + A.P.p_ref);
+    wp[4] = (R)(q[4 * N + op] + (double)rec[kRecP * N + op] + A.P.p_ref);
+    face_eval<2, R>(na, nb, wm, wp, kl, nk, true, Ph, hz_lo);
+#pragma unroll
+    for (int c = 0; c < 5; ++c) Wlow[c] = na.W(c);
   }
 
   for (int k = kbeg; k < kend; ++k) {
     // Every staging load of the plane in flight at once.
-    double vw[MW][6];
-    double vf[M1][sNF];
+    R vw[MW][6];
+    R vf[M1][sNF];
 #pragma unroll
     for (int r = 0; r < MW; ++r) {
       const int s = tid + r * NT;
       const int ia = wrap_or_out(i0 - 2 + s % PL::RX2, ni, D.per[0]);
       const int ja = wrap_or_out(j0 - 2 + s / PL::RX2, nj, D.per[1]);
 #pragma unroll
-      for (int c = 0; c < 6; ++c) vw[r][c] = 0.0;
+      for (int c = 0; c < 6; ++c) vw[r][c] = (R)0;
       if (s < PL::NW && ia >= 0 && ja >= 0) {
         const unsigned o = (unsigned)(ia + ni * (ja + nj * k));
+        const R pr = rec[kRecP * N + o];
 #pragma unroll
-        for (int c = 0; c < 5; ++c) vw[r][c] = q[c * N + o];
-        vw[r][5] = rec[kRecP * N + o];
+        for (int c = 0; c < 4; ++c) vw[r][c] = (R)q[c * N + o];
+        vw[r][4] = (R)(q[4 * N + o] + (double)pr + A.P.p_ref);
+        vw[r][5] = pr;
       }
     }
 #pragma unroll
@@ -624,7 +636,7 @@ k_stage_planes(StageArgs A, int kchunk) {
       const int ia = wrap_or_out(i0 - 1 + s % PL::RX1, ni, D.per[0]);
       const int ja = wrap_or_out(j0 - 1 + s / PL::RX1, nj, D.per[1]);
 #pragma unroll
-      for (int c = 0; c < sNF; ++c) vf[r][c] = 0.0;
+      for (int c = 0; c < sNF; ++c) vf[r][c] = (R)0;
       if (s < PL::N1 && ia >= 0 && ja >= 0) {
         const unsigned o = (unsigned)(ia + ni * (ja + nj * k));
         vf[r][sU] = rec[kRecU * N + o];
@@ -635,24 +647,21 @@ k_stage_planes(StageArgs A, int kchunk) {
         vf[r][sMut] = rec[kRecMut * N + o];
 #pragma unroll
         for (int c = 0; c < 9; ++c) vf[r][sS0 + c] = S[c * N + o];
-        vf[r][sJinv] = A.jinv[o];
+        vf[r][sJinv] = (R)A.jinv[o];
         const unsigned op = k + 1 == nk ? o - (unsigned)(nk - 1) * pl : o + pl;
         const unsigned om = k == 0 ? o + (unsigned)(nk - 1) * pl : o - pl;
 #pragma unroll
         for (int c = 0; c < 4; ++c)
-          vf[r][sDz + c] = 0.5 * (rec[(kRecU + c) * N + op] - rec[(kRecU + c) * N + om]);
+          vf[r][sDz + c] = (R)0.5 * (rec[(kRecU + c) * N + op] - rec[(kRecU + c) * N + om]);
       }
     }
     __syncthreads();  // the previous plane's face fluxes have been consumed
 #pragma unroll
     for (int r = 0; r < MW; ++r) {
       const int s = tid + r * NT;
-      if (s < PL::NW) {
+      if (s < PL::NW)
 #pragma unroll
-        for (int c = 0; c < 4; ++c) L.in.W[c][s] = vw[r][c];
-        L.in.W[4][s] = vw[r][4] + vw[r][5];
-        L.in.W[5][s] = vw[r][5];
-      }
+        for (int c = 0; c < 6; ++c) L.in.W[c][s] = vw[r][c];
     }
 #pragma unroll
     for (int r = 0; r < M1; ++r) {
@@ -664,71 +673,73 @@ k_stage_planes(StageArgs A, int kchunk) {
     __syncthreads();
 
     // Faces of the plane, held in registers until the staging space is free.
-    double hx[MX][5], hy[MY][5];
+    R hx[MX][5], hy[MY][5];
 #pragma unroll
     for (int r = 0; r < MX; ++r) {
       const int s = tid + r * NT;
 #pragma unroll
-      for (int c = 0; c < 5; ++c) hx[r][c] = 0.0;
+      for (int c = 0; c < 5; ++c) hx[r][c] = (R)0;
       const int fx = s % (TX + 1), fy = s / (TX + 1);
       const int ia = wrap_or_out(i0 - 1 + fx, ni, D.per[0]);
       const int ja = wrap_or_out(j0 + fy, nj, D.per[1]);
       if (s < PL::NX && ia >= 0 && ja >= 0 && (D.per[0] || ia < ni - 1)) {
         const unsigned oa = (unsigned)(ia + ni * (ja + nj * k));
         const unsigned ob = ia + 1 == ni ? oa - (unsigned)(ni - 1) : oa + 1;
-        FaceNode na, nb;
-        lds_node<TX, TY, 0>(L, fx, fy + 1, oa, rec, N, na);
-        lds_node<TX, TY, 0>(L, fx + 1, fy + 1, ob, rec, N, nb);
-        double wm[5], wp[5];
+        const LdsNode<TX, TY, 0, R> na{L, fx + PL::RX1 * (fy + 1), (fx + 1) + PL::RX2 * (fy + 2),
+                                       oa, rec, N};
+        const LdsNode<TX, TY, 0, R> nb{L, fx + 1 + PL::RX1 * (fy + 1),
+                                       (fx + 2) + PL::RX2 * (fy + 2), ob, rec, N};
+        R wm[5], wp[5];
 #pragma unroll
         for (int c = 0; c < 5; ++c) {
           wm[c] = L.in.W[c][fx + PL::RX2 * (fy + 2)];
           wp[c] = L.in.W[c][fx + 3 + PL::RX2 * (fy + 2)];
         }
-        face_core<0>(na, nb, wm, wp, ia, ni, D.per[0], Ph, hx[r]);
+        face_eval<0, R>(na, nb, wm, wp, ia, ni, D.per[0], Ph, hx[r]);
       }
     }
 #pragma unroll
     for (int r = 0; r < MY; ++r) {
       const int s = tid + r * NT;
 #pragma unroll
-      for (int c = 0; c < 5; ++c) hy[r][c] = 0.0;
+      for (int c = 0; c < 5; ++c) hy[r][c] = (R)0;
       const int fx = s % TX, fy = s / TX;
       const int ia = wrap_or_out(i0 + fx, ni, D.per[0]);
       const int ja = wrap_or_out(j0 - 1 + fy, nj, D.per[1]);
       if (s < PL::NY && ia >= 0 && ja >= 0 && (D.per[1] || ja < nj - 1)) {
         const unsigned oa = (unsigned)(ia + ni * (ja + nj * k));
         const unsigned ob = ja + 1 == nj ? oa - (unsigned)((nj - 1) * ni) : oa + ni;
-        FaceNode na, nb;
-        lds_node<TX, TY, 1>(L, fx + 1, fy, oa, rec, N, na);
-        lds_node<TX, TY, 1>(L, fx + 1, fy + 1, ob, rec, N, nb);
-        double wm[5], wp[5];
+        const LdsNode<TX, TY, 1, R> na{L, fx + 1 + PL::RX1 * fy, (fx + 2) + PL::RX2 * (fy + 1), oa,
+                                       rec, N};
+        const LdsNode<TX, TY, 1, R> nb{L, fx + 1 + PL::RX1 * (fy + 1),
+                                       (fx + 2) + PL::RX2 * (fy + 2), ob, rec, N};
+        R wm[5], wp[5];
 #pragma unroll
         for (int c = 0; c < 5; ++c) {
           wm[c] = L.in.W[c][fx + 2 + PL::RX2 * fy];
           wp[c] = L.in.W[c][fx + 2 + PL::RX2 * (fy + 3)];
         }
-        face_core<1>(na, nb, wm, wp, ja, nj, D.per[1], Ph, hy[r]);
+        face_eval<1, R>(na, nb, wm, wp, ja, nj, D.per[1], Ph, hy[r]);
       }
     }
     // Zeta face above the own node: lower node from LDS, upper node from global memory.
-    double hz[5] = {0, 0, 0, 0, 0};
-    double Wcur[5] = {0, 0, 0, 0, 0};
+    R hz[5] = {0, 0, 0, 0, 0};
+    R Wcur[5] = {0, 0, 0, 0, 0};
     if (mine) {
       const unsigned o = (unsigned)(i + ni * (j + nj * k));
-      FaceNode na, nb;
-      lds_node<TX, TY, 2>(L, a + 1, b + 1, o, rec, N, na);
+      const LdsNode<TX, TY, 2, R> na{L, a + 1 + PL::RX1 * (b + 1), (a + 2) + PL::RX2 * (b + 2), o,
+                                     rec, N};
       const int kp = k + 1 == nk ? 0 : k + 1;
       const int kp2 = kp + 1 == nk ? 0 : kp + 1;
-      global_node_z(A, i, j, kp, nb);
+      const GlobalNodeZ<R> nb(A, i, j, kp);
       const unsigned o2 = (unsigned)(i + ni * (j + nj * kp2));
-      double wp[5];
+      R wp[5];
 #pragma unroll
-      for (int c = 0; c < 5; ++c) wp[c] = q[c * N + o2];
-      wp[4] += rec[kRecP * N + o2];
-      face_core<2>(na, nb, Wlow, wp, k, nk, true, Ph, hz);
+      for (int c = 0; c < 4; ++c) wp[c] = (R)q[c * N + o2];
+      wp[4] = (R)(q[4 * N + o2] + (double)rec[kRecP * N + o2] + A.P.p_ref);
+      face_eval<2, R>(na, nb, Wlow, wp, k, nk, true, Ph, hz);
 #pragma unroll
-      for (int c = 0; c < 5; ++c) Wcur[c] = na.W[c];
+      for (int c = 0; c < 5; ++c) Wcur[c] = na.W(c);
     }
     __syncthreads();  // staging reads done: the space now takes the face fluxes
 #pragma unroll
@@ -754,14 +765,14 @@ k_stage_planes(StageArgs A, int kchunk) {
         if (A.mode == 1) fac = A.alpha * A.dt[0] * A.jac[o];
 #pragma unroll
         for (int c = 0; c < 5; ++c) {
-          double rr = 0.0;
+          R rr = (R)0;
           rr += L.H[c][sx + 1] - L.H[c][sx];
           rr += L.H[c][sy + TX] - L.H[c][sy];
           rr += hz[c] - hz_lo[c];
           if (A.mode == 0)
-            A.out[c * N + o] = rr;
+            A.out[c * N + o] = (double)rr;
           else
-            A.out[c * N + o] = A.q0[c * N + o] - fac * rr;
+            A.out[c * N + o] = A.q0[c * N + o] - fac * (double)rr;
         }
       } else if (A.mode == 0) {
 #pragma unroll
@@ -793,7 +804,10 @@ hipError_t launch_tile(const StageArgs& A, hipStream_t s, int kmin) {
 hipError_t launch_nodes(const StageArgs& A, hipStream_t s) {
   dim3 block(64, 4, 1);
   dim3 grid((A.D.n[0] + 63) / 64, (A.D.n[1] + 3) / 4, A.D.n[2]);
-  hipLaunchKernelGGL(k_nodes, grid, block, 0, s, A);
+  if (A.mixed)
+    hipLaunchKernelGGL(k_nodes<float>, grid, block, 0, s, A);
+  else
+    hipLaunchKernelGGL(k_nodes<double>, grid, block, 0, s, A);
   return hipGetLastError();
 }
 
@@ -803,19 +817,27 @@ const char* const kTileNames[kNumTiles] = {"32x8", "64x4", "16x16", "32x4", "64x
                                            "planes16x16", "planes32x8", "planes16x8/w2",
                                            "planes16x16/w2"};
 
-template <int TX, int TY, int WPE = 1>
+template <int TX, int TY, int WPE = 1, typename R = double>
 hipError_t launch_planes(const StageArgs& A, hipStream_t s, int kmin) {
   const int gx = (A.D.n[0] + TX - 1) / TX, gy = (A.D.n[1] + TY - 1) / TY;
   int nz = (1024 + gx * gy - 1) / (gx * gy);
   nz = max(1, min(nz, A.D.n[2] / kmin));
   const int kchunk = (A.D.n[2] + nz - 1) / nz;
   nz = (A.D.n[2] + kchunk - 1) / kchunk;
-  hipLaunchKernelGGL((k_stage_planes<TX, TY, WPE>), dim3(gx, gy, nz), dim3(TX * TY), 0, s, A, kchunk);
+  hipLaunchKernelGGL((k_stage_planes<TX, TY, WPE, R>), dim3(gx, gy, nz), dim3(TX * TY), 0, s, A, kchunk);
   return hipGetLastError();
 }
 
 hipError_t launch_stage(const StageArgs& A, hipStream_t s) {
   const int kmin = A.kmin > 0 ? A.kmin : 8;
+  if (A.mixed) switch (A.tile) {
+      case 10: return launch_planes<32, 4, 1, float>(A, s, kmin);
+      case 11: return launch_planes<16, 8, 1, float>(A, s, kmin);
+      case 12: return launch_planes<16, 16, 1, float>(A, s, kmin);
+      case 14: return launch_planes<16, 8, 2, float>(A, s, kmin);
+      case 15: return launch_planes<16, 16, 2, float>(A, s, kmin);
+      default: return launch_planes<32, 8, 1, float>(A, s, kmin);
+    }
   // The plane-staged kernel needs a periodic z direction (true of every supported set).
   if (A.D.per[2]) switch (A.tile) {
       case 10: return launch_planes<32, 4>(A, s, kmin);
