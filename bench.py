@@ -1,12 +1,13 @@
 #!/usr/bin/env python3
 """Throughput benchmark of the LES hot path on one MI355X.
 
-One benchmark step is one full Runge-Kutta step (time-step reduction, five stage kernels,
-boundary conditions) of the synthetic M = 1.4 jet on the 256 x 128 x 128 curvilinear grid in
-FP64, with the state resident in HBM. The JSON line reports Mcell-RKstage/s (updated nodes x
-5 stages x steps / wall time), the roofline position of the stage kernel (timed live with
-HIP events on the stream it runs on), and the CPU oracle timed on a bounded sample of the
-same workload.
+One benchmark step is one full Runge-Kutta step (time-step reduction, five stages of two
+kernels each, boundary conditions) of the synthetic M = 1.4 jet on the 256 x 128 x 128
+curvilinear grid in FP64, with the state resident in HBM. The JSON line reports
+Mcell-RKstage/s (updated nodes x 5 stages x steps / wall time), the roofline position of the
+dominant kernel (the face kernel, timed live with HIP events on the stream it runs on), the
+same workload in the mixed-precision form, and the CPU oracle timed on a bounded sample of
+the same workload.
 """
 import argparse
 import hashlib
@@ -19,11 +20,13 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-# Algorithmic bytes per updated node and stage of the fused FP64 stage kernel: read the
-# stage input Q^(l-1) (40 B) and Q^(0) (40 B), write Q^(l) (40 B), read the metrics
-# S (72 B) and J^-1 (8 B); stage 1 reads Q^(0) once (160 B), stages 2-5 move 200 B.
-BYTES_PER_CELL_STAGE = {"fp64": (160.0 + 4 * 200.0) / 5.0}
+# Algorithmic bytes per updated node and Runge-Kutta stage (metrics stored, halos served on
+# chip): read the stage input Q^(l-1) (40 B) and Q^(0) (40 B), write Q^(l) (40 B), read the
+# metrics S and J^-1; stage 1 reads Q^(0) once. FP64: S 72 B + J^-1 8 B, stage 1 160 B,
+# stages 2-5 200 B. Mixed: S stored in FP32 (36 B), stage 1 124 B, stages 2-5 164 B.
+BYTES_PER_CELL_STAGE = {"fp64": (160.0 + 4 * 200.0) / 5.0, "mixed": (124.0 + 4 * 164.0) / 5.0}
 STAGE_SOURCES = ["paper_2212_12365_amd/csrc/les_stage.hip", "paper_2212_12365_amd/csrc/les_device.h"]
+JET_GRID = (256, 128, 128)
 
 
 def stage_kernel_hash():
@@ -56,10 +59,34 @@ def cpu_baseline(params, xyz, q, steps):
     o.step(q, steps, cfl=0.5)
     t = time.perf_counter() - t0
     upd = (params.ni - 2) * (params.nj - 2) * params.nk
-    return {"value": upd * 5 * steps / t / 1e6, "unit": "Mcell-RKstage/s", "cores": threads,
-            "kind": "oracle",
-            "sample": f"{steps} RK step(s) (= {5 * steps} stages) of the same jet "
-                      f"{params.ni}x{params.nj}x{params.nk} FP64 workload, {t:.1f} s"}
+    return {"value": round(upd * 5 * steps / t / 1e6, 3), "unit": "Mcell-RKstage/s",
+            "cores": threads, "kind": "oracle",
+            "sample": f"{steps} RK steps (= {5 * steps} stages, with time-step reduction and "
+                      f"boundary conditions) of the same jet {params.ni}x{params.nj}x{params.nk} "
+                      f"FP64 workload, {t:.1f} s on {threads} OpenMP threads"}
+
+
+def run_form(torch, params, xyz, q, steps, warmup):
+    """Times `steps` RK steps of one context; returns the measured figures."""
+    from paper_2212_12365_amd.lesmi import Context
+    ctx = Context(params, xyz)
+    g = torch.from_numpy(q).to("cuda")
+    ctx.apply_bc(g)
+    upd = ctx.updated_nodes()
+    if warmup:
+        ctx.step(g, warmup, cfl=0.5)
+    torch.cuda.synchronize()
+    ctx.profile(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ctx.step(g, steps, cfl=0.5)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    nodes_ms, faces_ms, stages = ctx.profile_read()
+    ctx.profile(False)
+    ctx.close()
+    return {"updated_nodes": upd, "wall_s": wall, "nodes_ms": nodes_ms, "faces_ms": faces_ms,
+            "stages": stages, "rate": upd * 5 * steps / wall / 1e6}
 
 
 def copy_calibration(gib=1.0, reps=5):
@@ -80,7 +107,9 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=10)
-    ap.add_argument("--cpu-steps", type=int, default=2,
+    ap.add_argument("--no-forms", dest="forms", action="store_false",
+                    help="time the FP64 form only (skip the mixed-precision run)")
+    ap.add_argument("--cpu-steps", type=int, default=15,
                     help="RK steps of the oracle timed for the CPU baseline (0 = skip)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a 1 GiB device copy (counter calibration) and exit")
@@ -98,40 +127,33 @@ def main():
         return
 
     import synthetic as sy
-    from paper_2212_12365_amd.lesmi import Context
 
-    n = (256, 128, 128)
-    params, xyz, q = sy.make_case("jet", n, seed=0)
-    ctx = Context(params, xyz)
-    g = torch.from_numpy(q).to("cuda")
-    ctx.apply_bc(g)
-    upd = ctx.updated_nodes()
-    if args.warmup:
-        ctx.step(g, args.warmup, cfl=0.5)
-    torch.cuda.synchronize()
-
-    ctx.profile(True)
-    stream = torch.cuda.current_stream()
-    e0 = torch.cuda.Event(enable_timing=True)
-    e1 = torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    e0.record(stream)
-    ctx.step(g, args.steps, cfl=0.5)
-    e1.record(stream)
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    stage_ms, launches = ctx.profile_read()
-    ctx.profile(False)
-    ev_ms = e0.elapsed_time(e1)
-
-    value = upd * 5 * args.steps / wall / 1e6
+    params, xyz, q = sy.make_case("jet", JET_GRID, seed=0)
+    f64 = run_form(torch, params, xyz, q, args.steps, args.warmup)
+    upd = f64["updated_nodes"]
+    value = f64["rate"]
+    # Dominant kernel: the face kernel (fluxes, flux differences, stage update), timed by
+    # HIP events recorded on the stream it is launched on.
     bpc = BYTES_PER_CELL_STAGE["fp64"]
-    avg_s = stage_ms / 1e3 / max(launches, 1)
+    face_s = f64["faces_ms"] / 1e3 / max(f64["stages"], 1)
+    node_s = f64["nodes_ms"] / 1e3 / max(f64["stages"], 1)
     per_launch = bpc * upd
-    achieved = per_launch / avg_s / 1e9
+    achieved = per_launch / face_s / 1e9
     khash = stage_kernel_hash()
-    traffic = measured_traffic(khash)
+    forms = {"fp64": {"value": round(value, 3),
+                      "hbm_roofline_pct": round(100 * value * 1e6 * bpc / (HBM_PEAK_GBS * 1e9), 2),
+                      "face_kernel_us": round(face_s * 1e6, 2),
+                      "node_kernel_us": round(node_s * 1e6, 2)}}
+    if args.forms:
+        mp = params.replace(precision=1)
+        mx = run_form(torch, mp, xyz, q, args.steps, args.warmup)
+        bm = BYTES_PER_CELL_STAGE["mixed"]
+        forms["mixed"] = {
+            "value": round(mx["rate"], 3),
+            "hbm_roofline_pct": round(100 * mx["rate"] * 1e6 * bm / (HBM_PEAK_GBS * 1e9), 2),
+            "face_kernel_us": round(mx["faces_ms"] * 1e3 / max(mx["stages"], 1), 2),
+            "node_kernel_us": round(mx["nodes_ms"] * 1e3 / max(mx["stages"], 1), 2),
+            "speedup_vs_fp64": round(mx["rate"] / value, 3)}
     out = {
         "metric": "Mcell-RKstage updates/s and % HBM roofline, FP64 vs mixed vs batched",
         "value": round(value, 3),
@@ -139,26 +161,22 @@ def main():
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": round(wall * 1e3 / args.steps, 4),
+        "ms_per_step": round(f64["wall_s"] * 1e3 / args.steps, 4),
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f64",
         "data": "synthetic",
-        "config": {"workload": "jet 256x128x128 FP64, CFL 0.5",
-                   "grid": list(n), "updated_nodes": upd, "precision": "fp64",
-                   "closure": "smagorinsky",
-                   "hbm_roofline_pct_whole_step": round(100 * value * 1e6 * bpc / (HBM_PEAK_GBS * 1e9), 2),
-                   "event_ms_per_step": round(ev_ms / args.steps, 4)},
+        "config": {"workload": "jet 256x128x128 FP64, CFL 0.5, Smagorinsky",
+                   "grid": list(JET_GRID), "updated_nodes": upd, "forms": forms},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                     "traffic": traffic,
-                     "kernel": "RK stage kernel(s)",
-                     "avg_launch_us": round(avg_s * 1e6, 2), "launches": launches,
+                     "traffic": measured_traffic(khash),
+                     "kernel": "k_stage_planes (face fluxes, flux differences, stage update)",
+                     "avg_launch_us": round(face_s * 1e6, 2), "launches": f64["stages"],
                      "algorithmic_bytes_per_launch": per_launch,
                      "kernel_source_hash": khash},
     }
-    ctx.close()
     if args.cpu_steps > 0:
         out["cpu_baseline"] = cpu_baseline(params, xyz, q, args.cpu_steps)
     print(json.dumps(out), flush=True)

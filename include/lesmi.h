@@ -131,13 +131,15 @@ int les_set_tuning(les_ctx* ctx, int tile, int kmin);
 int les_tuning_count(void);
 const char* les_tuning_name(int tile);
 
-/* Instrumentation: with enable != 0, les_step records a HIP event on its stream before and
- * after every Runge-Kutta stage kernel launch (the residual and the stage update, boundary
- * conditions excluded). les_profile_read waits for the last recorded event, returns the
- * summed stage-kernel time in milliseconds and the number of timed launches since the last
- * read (or since les_profile), and resets the record. */
+/* Instrumentation: with enable != 0, les_step records HIP events on its stream around the
+ * two kernels of every Runge-Kutta stage: the node-record kernel (primitives, eddy
+ * viscosity, spectral radii, sensors) and the face kernel (fluxes, flux differences and the
+ * stage update); boundary conditions and the time-step reduction are excluded.
+ * les_profile_read waits for the last recorded event and returns, since the last read (or
+ * since les_profile), the summed node-kernel and face-kernel times in milliseconds and the
+ * number of timed stages, then resets the record. Either time pointer may be NULL. */
 int les_profile(les_ctx* ctx, int enable);
-int les_profile_read(les_ctx* ctx, double* total_ms, long long* launches);
+int les_profile_read(les_ctx* ctx, double* nodes_ms, double* faces_ms, long long* stages);
 
 void les_destroy(les_ctx* ctx);
 const char* les_last_error(const les_ctx* ctx);

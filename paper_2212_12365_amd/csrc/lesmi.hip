@@ -566,6 +566,19 @@ StageArgs stage_args(les_ctx* c, const double* q) {
   return A;
 }
 
+// Records the next event of the profiling ring (three per stage: before the node kernel,
+// between the two kernels, after the face kernel).
+int prof_mark(les_ctx* c, hipStream_t s) {
+  if (!c->prof) return LES_OK;
+  if (c->nrec == c->ev.size()) {
+    hipEvent_t e;
+    HIP_TRY(c, hipEventCreate(&e));
+    c->ev.push_back(e);
+  }
+  HIP_TRY(c, hipEventRecord(c->ev[c->nrec++], s));
+  return LES_OK;
+}
+
 // One residual evaluation: node records, then faces and flux differences with either the
 // residual (mode 0) or the Runge-Kutta stage update (mode 1) as the epilogue.
 int run_stage(les_ctx* c, const double* q, int mode, double* out, const double* q0,
@@ -576,24 +589,19 @@ int run_stage(les_ctx* c, const double* q, int mode, double* out, const double* 
   A.q0 = q0;
   A.dt = c->d_dt;
   A.alpha = alpha;
+  const bool timed = mode == 1;
+  int rc = timed ? prof_mark(c, s) : LES_OK;
+  if (rc) return rc;
   hipError_t e = launch_nodes(A, s);
+  if (e == hipSuccess && timed) rc = prof_mark(c, s);
+  if (rc) return rc;
   if (e == hipSuccess) e = launch_stage(A, s);
+  if (e == hipSuccess && timed) rc = prof_mark(c, s);
+  if (rc) return rc;
   if (e != hipSuccess) {
     c->err = std::string("stage kernels: ") + hipGetErrorString(e);
     return LES_EHIP;
   }
-  return LES_OK;
-}
-
-// Records the next event of the profiling ring (start/end pairs around each stage).
-int prof_mark(les_ctx* c, hipStream_t s) {
-  if (!c->prof) return LES_OK;
-  if (c->nrec == c->ev.size()) {
-    hipEvent_t e;
-    HIP_TRY(c, hipEventCreate(&e));
-    c->ev.push_back(e);
-  }
-  HIP_TRY(c, hipEventRecord(c->ev[c->nrec++], s));
   return LES_OK;
 }
 
@@ -739,11 +747,7 @@ int les_step(les_ctx* c, double* q, int nsteps, double cfl, double dt_fixed, dou
     const double* in = q;
     for (int l = 0; l < 5; ++l) {
       double* outb = (l == 4) ? q : ((l % 2 == 0) ? c->qa : c->qb);
-      int rc = prof_mark(c, s);
-      if (rc) return rc;
-      rc = run_stage(c, in, 1, outb, q, alpha[l], s);
-      if (rc) return rc;
-      rc = prof_mark(c, s);
+      int rc = run_stage(c, in, 1, outb, q, alpha[l], s);
       if (rc) return rc;
       rc = run_bc(c, outb, s);
       if (rc) return rc;
@@ -813,17 +817,20 @@ int les_profile(les_ctx* c, int enable) {
   return LES_OK;
 }
 
-int les_profile_read(les_ctx* c, double* total_ms, long long* launches) {
-  if (!c || !total_ms || !launches) return LES_EINVAL;
-  double tot = 0.0;
-  if (c->nrec >= 2) HIP_TRY(c, hipEventSynchronize(c->ev[c->nrec - 1]));
-  for (size_t r = 0; r + 1 < c->nrec; r += 2) {
-    float ms = 0.f;
-    HIP_TRY(c, hipEventElapsedTime(&ms, c->ev[r], c->ev[r + 1]));
-    tot += ms;
+int les_profile_read(les_ctx* c, double* nodes_ms, double* faces_ms, long long* stages) {
+  if (!c || !stages) return LES_EINVAL;
+  double tn = 0.0, tf = 0.0;
+  if (c->nrec >= 3) HIP_TRY(c, hipEventSynchronize(c->ev[c->nrec - 1]));
+  for (size_t r = 0; r + 2 < c->nrec; r += 3) {
+    float a = 0.f, b = 0.f;
+    HIP_TRY(c, hipEventElapsedTime(&a, c->ev[r], c->ev[r + 1]));
+    HIP_TRY(c, hipEventElapsedTime(&b, c->ev[r + 1], c->ev[r + 2]));
+    tn += a;
+    tf += b;
   }
-  *total_ms = tot;
-  *launches = (long long)(c->nrec / 2);
+  if (nodes_ms) *nodes_ms = tn;
+  if (faces_ms) *faces_ms = tf;
+  *stages = (long long)(c->nrec / 3);
   c->nrec = 0;
   return LES_OK;
 }

@@ -72,7 +72,7 @@ def load():
         lib.les_tuning_name.argtypes = [ctypes.c_int]
         lib.les_tuning_name.restype = ctypes.c_char_p
         lib.les_profile.argtypes = [vp, ctypes.c_int]
-        lib.les_profile_read.argtypes = [vp, dp, ctypes.POINTER(ctypes.c_longlong)]
+        lib.les_profile_read.argtypes = [vp, dp, dp, ctypes.POINTER(ctypes.c_longlong)]
         lib.les_destroy.argtypes = [vp]
         lib.les_destroy.restype = None
         lib.les_last_error.argtypes = [vp]
@@ -207,12 +207,13 @@ class Context:
         self._check(self.lib.les_profile(self.handle, int(bool(enable))), "les_profile")
 
     def profile_read(self):
-        """(total stage-kernel milliseconds, number of timed launches) since the last read."""
-        ms = ctypes.c_double(0.0)
+        """(node-kernel ms, face-kernel ms, timed stages) summed since the last read."""
+        tn = ctypes.c_double(0.0)
+        tf = ctypes.c_double(0.0)
         n = ctypes.c_longlong(0)
-        self._check(self.lib.les_profile_read(self.handle, ctypes.byref(ms), ctypes.byref(n)),
-                    "les_profile_read")
-        return ms.value, n.value
+        self._check(self.lib.les_profile_read(self.handle, ctypes.byref(tn), ctypes.byref(tf),
+                                              ctypes.byref(n)), "les_profile_read")
+        return tn.value, tf.value, n.value
 
     def updated_nodes(self):
         return int(self.lib.les_updated_nodes(self.handle))
