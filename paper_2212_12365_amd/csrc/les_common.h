@@ -66,7 +66,7 @@ struct les_ctx {
   float* rec32 = nullptr;
   float* S32 = nullptr;
   // Stage kernel launch shape (index into the tile table) and smallest z-chunk depth.
-  int tile = 13;
+  int tile = 0;
   int kmin = 8;
 
   // Scalars: dt, min-ratio bits, status flags, reduction partials.

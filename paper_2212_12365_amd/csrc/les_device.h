@@ -19,6 +19,12 @@ struct Phys {
   // terms sum to p_ref * sum_d delta_d S_d, which the conservative metrics make vanish at
   // every updated node.
   double p_ref;
+  // Reference dissipated vector (rho, rho u, rho v, rho w, e + p) of the free stream,
+  // subtracted in FP64 before the FP32 cast in the mixed form (0 in FP64). Differences of
+  // W are unchanged; the FP32 rounding error of W then scales with |W - W_ref| rather than
+  // |W|, which keeps the fourth-difference dissipation of a near-uniform free stream free
+  // of rounding noise.
+  double wref[5];
 };
 
 // The same constants in the arithmetic type of a kernel (double, or float for the mixed
@@ -26,10 +32,13 @@ struct Phys {
 template <typename R>
 struct PhysT {
   R gamma, gm1, inv_gm1, inv_re, inv_pr, inv_prs, s1, s1p1, cs2, k2, k4;
+  R wref[5];
   __device__ __host__ explicit PhysT(const Phys& P)
       : gamma((R)P.gamma), gm1((R)P.gm1), inv_gm1((R)P.inv_gm1), inv_re((R)P.inv_re),
         inv_pr((R)P.inv_pr), inv_prs((R)P.inv_prs), s1((R)P.s1), s1p1((R)P.s1p1),
-        cs2((R)P.cs2), k2((R)P.k2), k4((R)P.k4) {}
+        cs2((R)P.cs2), k2((R)P.k2), k4((R)P.k4) {
+    for (int c = 0; c < 5; ++c) wref[c] = (R)P.wref[c];
+  }
 };
 
 // Primitive variables of a node (paper, LES formulation: equation of state and System-I

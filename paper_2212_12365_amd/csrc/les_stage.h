@@ -34,11 +34,11 @@ struct StageArgs {
   const double* q0;
   const double* dt;
   double alpha;
-  int tile;   // k_stage tile shape index into kTileNames
+  int tile;   // k_stage_planes tile shape, index into kTileNames
   int kmin;   // smallest z-chunk depth (0 = default)
 };
 
-constexpr int kNumTiles = 16;
+constexpr int kNumTiles = 6;
 extern const char* const kTileNames[kNumTiles];
 
 hipError_t launch_nodes(const StageArgs& A, hipStream_t s);
