@@ -14,8 +14,9 @@
  * xi (i), eta (j), zeta (k); for the jet these are axial, radial and azimuthal.
  *
  * Ownership. The caller owns every array passed in; the context owns the grid metrics,
- * the Runge-Kutta stage buffers, the boundary data and the time-step scalar. No entry
- * point other than les_init_grid and les_destroy allocates or frees memory.
+ * the Runge-Kutta stage buffers, the boundary data and the time-step scalar. Device memory
+ * is allocated or freed only by les_init_grid, les_destroy and the batch calls
+ * les_batch_create, les_batch_set_tuning, les_batch_autotune and les_batch_destroy.
  *
  * Streams. `stream` is a hipStream_t (NULL = the null stream). Every call except
  * les_init_grid and les_destroy is asynchronous on that stream, and may be issued from
@@ -141,7 +142,54 @@ const char* les_tuning_name(int tile);
 int les_profile(les_ctx* ctx, int enable);
 int les_profile_read(les_ctx* ctx, double* nodes_ms, double* faces_ms, long long* stages);
 
+/* Autotuner of a single context: times every stage-kernel tile shape with z-chunk depths
+ * 4, 8 and 16 on residual evaluations of q (DEVICE [5][N], not modified) and keeps the
+ * fastest (les_set_tuning). tile and kmin (HOST, may be NULL) receive the choice.
+ * Synchronises the stream. */
+int les_autotune(les_ctx* ctx, const double* q, int* tile, int* kmin, void* stream);
+
 void les_destroy(les_ctx* ctx);
+
+/* ---------------------------------------------------------------------------------------
+ * Batched ensembles: n independent contexts (for instance seeded jet realisations on grids
+ * of different sizes) advanced together. Each kernel of a Runge-Kutta step runs as one
+ * persistent launch over a work list spanning every member, and a whole step is captured
+ * once in a HIP graph and replayed. Every member keeps its own time step (its own CFL
+ * reduction). The arithmetic per node and face is that of les_step, so each member's result
+ * equals its single-context run.
+ *
+ * The batch borrows its members' device buffers (metrics, stage buffers, node records,
+ * time-step scalars): while a batch exists its members must not be stepped on their own,
+ * and they must outlive it. All members share one precision and device.
+ * ------------------------------------------------------------------------------------- */
+typedef struct les_batch les_batch;
+
+/* members: HOST array of n context handles. On failure *out may still be set so that
+ * les_batch_last_error can be read; les_batch_destroy it. */
+int les_batch_create(les_ctx* const* members, int n, les_batch** out);
+
+/* Advances every member by nsteps steps (as les_step: cfl > 0 gives each member
+ * dt = cfl * its own reduction, else dt_fixed for all). q: HOST array of n DEVICE state
+ * pointers [5][N_m], each satisfying its boundary conditions on entry. dt_last: HOST [n] or
+ * NULL. Synchronises once, at the end. Returns LES_ENONFINITE naming the failing members. */
+int les_batch_step(les_batch* b, double* const* q, int nsteps, double cfl, double dt_fixed,
+                   double* dt_last, void* stream);
+
+/* Stage-kernel launch shape of the batch (the tile table of les_tuning_name; kmin >= 1). */
+int les_batch_set_tuning(les_batch* b, int tile, int kmin);
+int les_batch_get_tuning(const les_batch* b, int* tile, int* kmin);
+
+/* Autotuner of the batch: times every tile shape with z-chunk depths 4, 8 and 16 on one
+ * persistent residual launch over all members (states q, not modified) and keeps the
+ * fastest. Synchronises the stream. */
+int les_batch_autotune(les_batch* b, double* const* q, int* tile, int* kmin, void* stream);
+
+/* enable != 0 (the default): steps replay a captured graph; 0: launches are issued one by
+ * one (the same kernels). */
+int les_batch_set_graph(les_batch* b, int enable);
+
+void les_batch_destroy(les_batch* b);
+const char* les_batch_last_error(const les_batch* b);
 const char* les_last_error(const les_ctx* ctx);
 
 #ifdef __cplusplus

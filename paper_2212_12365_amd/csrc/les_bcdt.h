@@ -1,0 +1,237 @@
+// Boundary-condition, time-step and state-check device functions of the lesmi library
+// (gfx950), shared by the single-grid kernels and the persistent batch kernels. Each
+// function covers one block's or one thread's part of the work, given its coordinates.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "les_common.h"
+
+namespace lesmi {
+
+// ---------------------------------------------------------------------------------------
+// Boundary conditions (paper, Boundary Conditions).
+// ---------------------------------------------------------------------------------------
+
+// Far-field Riemann state from the interior state qe and the unit outward normal n.
+__device__ void farfield_state(const Phys& P, const BcData& B, const double* qe,
+                               const double* n, double* qo) {
+  double g = P.gamma;
+  double re = qe[0];
+  double ue[3] = {qe[1] / re, qe[2] / re, qe[3] / re};
+  double pe = P.gm1 * (qe[4] - 0.5 * re * (ue[0] * ue[0] + ue[1] * ue[1] + ue[2] * ue[2]));
+  double ae = sqrt(g * pe / re);
+  double ainf = sqrt(g * B.p_inf / B.rho_inf);
+  double qne = ue[0] * n[0] + ue[1] * n[1] + ue[2] * n[2];
+  double qninf = B.u_inf[0] * n[0] + B.u_inf[1] * n[1] + B.u_inf[2] * n[2];
+  double rp = qne + 2.0 * ae * P.inv_gm1;
+  double rm = qninf - 2.0 * ainf * P.inv_gm1;
+  double qnf = 0.5 * (rp + rm);
+  double af = 0.25 * P.gm1 * (rp - rm);
+  double mn = qne / ae;
+  double uf[3], rf, pf;
+  if (mn >= 1.0) {
+    for (int c = 0; c < 5; ++c) qo[c] = qe[c];
+    return;
+  } else if (mn >= 0.0) {
+    for (int c = 0; c < 3; ++c) uf[c] = ue[c] + (qnf - qne) * n[c];
+    rf = pow(pow(re, g) * af * af / (g * pe), P.inv_gm1);
+    pf = rf * af * af / g;
+  } else if (mn > -1.0) {
+    for (int c = 0; c < 3; ++c) uf[c] = B.u_inf[c] + (qnf - qninf) * n[c];
+    rf = pow(pow(B.rho_inf, g) * af * af / (g * B.p_inf), P.inv_gm1);
+    pf = rf * af * af / g;
+  } else {
+    for (int c = 0; c < 3; ++c) uf[c] = B.u_inf[c];
+    rf = B.rho_inf;
+    pf = B.p_inf;
+  }
+  qo[0] = rf;
+  qo[1] = rf * uf[0];
+  qo[2] = rf * uf[1];
+  qo[3] = rf * uf[2];
+  qo[4] = pf * P.inv_gm1 + 0.5 * rf * (uf[0] * uf[0] + uf[1] * uf[1] + uf[2] * uf[2]);
+}
+
+// Centreline means of the first ring, summed in k order (paper, Centerline Boundary
+// Condition). One block per axial station i: the ring is staged through LDS in chunks and
+// five threads add it up sequentially, so the sum order is k = 0, 1, ..., nk-1.
+constexpr int kAxisChunk = 1024;
+__device__ __forceinline__ void axis_mean_block(const Dims& D, const double* __restrict__ q,
+                                                double* __restrict__ axis, int i,
+                                                double (&ring)[5][kAxisChunk]) {
+  const long long N = D.N;
+  const int nk = D.n[2];
+  double sum = 0.0;  // thread c < 5 accumulates component c
+  for (int kb = 0; kb < nk; kb += kAxisChunk) {
+    int len = min(kAxisChunk, nk - kb);
+    for (int t = threadIdx.x; t < 5 * len; t += blockDim.x) {
+      int c = t / len, k = kb + t % len;
+      ring[c][k - kb] = q[(long long)c * N + nid(D, i, 1, k)];
+    }
+    __syncthreads();
+    if (threadIdx.x < 5)
+      for (int k = 0; k < len; ++k) sum += ring[threadIdx.x][k];
+    __syncthreads();
+  }
+  if (threadIdx.x < 5) axis[(long long)threadIdx.x * D.n[0] + i] = sum / (double)nk;
+}
+
+__device__ __forceinline__ void load_q(const double* q, long long N, long long id, double* o) {
+  for (int c = 0; c < 5; ++c) o[c] = q[(long long)c * N + id];
+}
+
+// One thread per boundary node. Far field (j = nj-1, 1 <= i <= ni-2), centreline (j = 0,
+// 1 <= i <= ni-2), entrance (i = 0), exit (i = ni-1). Each boundary value is composed from
+// updated nodes only, reproducing the order far field -> centreline -> entrance -> exit.
+__device__ __forceinline__ void bc_node(const Dims& D, const Phys& P, const BcData& B,
+                                        double* __restrict__ q, long long t) {
+  int ni = D.n[0], nj = D.n[1], nk = D.n[2];
+  long long N = D.N;
+  long long nrow = (long long)(ni - 2) * nk;
+  long long nface = (long long)nj * nk;
+  double qe[5], qo[5], n[3];
+  auto ff_normal = [&](int i, int k, double* o) {
+    long long s = (long long)ni * nk, off = i + (long long)ni * k;
+    o[0] = B.nff[off];
+    o[1] = B.nff[s + off];
+    o[2] = B.nff[2 * s + off];
+  };
+  // Far-field state of node (i, nj-1, k), from its interior neighbour.
+  auto farfield_node = [&](int i, int k, double* o) {
+    double qi[5], nn[3];
+    load_q(q, N, nid(D, i, nj - 2, k), qi);
+    ff_normal(i, k, nn);
+    farfield_state(P, B, qi, nn, o);
+  };
+  // State of node (i, j, k) after the far field and centreline conditions.
+  auto after_j = [&](int i, int j, int k, double* o) {
+    if (j == nj - 1)
+      farfield_node(i, k, o);
+    else if (j == 0)
+      for (int c = 0; c < 5; ++c) o[c] = B.axis[(long long)c * ni + i];
+    else
+      load_q(q, N, nid(D, i, j, k), o);
+  };
+  long long id;
+  if (t < nrow) {  // far field
+    int i = 1 + (int)(t % (ni - 2)), k = (int)(t / (ni - 2));
+    farfield_node(i, k, qo);
+    id = nid(D, i, nj - 1, k);
+  } else if (t < 2 * nrow) {  // centreline
+    long long o = t - nrow;
+    int i = 1 + (int)(o % (ni - 2)), k = (int)(o / (ni - 2));
+    for (int c = 0; c < 5; ++c) qo[c] = B.axis[(long long)c * ni + i];
+    id = nid(D, i, 0, k);
+  } else if (t < 2 * nrow + nface) {  // entrance
+    long long o = t - 2 * nrow;
+    int j = (int)(o % nj), k = (int)(o / nj);
+    id = nid(D, 0, j, k);
+    if (B.jetmask[o]) {
+      double uj = B.mach_jet;
+      qo[0] = 1.0;
+      qo[1] = uj;
+      qo[2] = 0.0;
+      qo[3] = 0.0;
+      qo[4] = (1.0 / P.gamma) * P.inv_gm1 + 0.5 * uj * uj;
+    } else {
+      after_j(1, j, k, qe);
+      n[0] = B.nin[o];
+      n[1] = B.nin[nface + o];
+      n[2] = B.nin[2 * nface + o];
+      farfield_state(P, B, qe, n, qo);
+    }
+  } else if (t < 2 * nrow + 2 * nface) {  // exit
+    long long o = t - 2 * nrow - nface;
+    int j = (int)(o % nj), k = (int)(o / nj);
+    id = nid(D, ni - 1, j, k);
+    after_j(ni - 2, j, k, qe);
+    n[0] = B.nex[o];
+    n[1] = B.nex[nface + o];
+    n[2] = B.nex[2 * nface + o];
+    double re = qe[0];
+    double ue[3] = {qe[1] / re, qe[2] / re, qe[3] / re};
+    double pe = P.gm1 * (qe[4] - 0.5 * re * (ue[0] * ue[0] + ue[1] * ue[1] + ue[2] * ue[2]));
+    double ae = sqrt(P.gamma * pe / re);
+    double mn = (ue[0] * n[0] + ue[1] * n[1] + ue[2] * n[2]) / ae;
+    if (mn >= 1.0) {
+      for (int c = 0; c < 5; ++c) qo[c] = qe[c];
+    } else {
+      double eint = pe / (P.gm1 * re);
+      double rb = B.p_inf / (P.gm1 * eint);
+      qo[0] = rb;
+      qo[1] = rb * ue[0];
+      qo[2] = rb * ue[1];
+      qo[3] = rb * ue[2];
+      qo[4] = B.p_inf * P.inv_gm1 + 0.5 * rb * (ue[0] * ue[0] + ue[1] * ue[1] + ue[2] * ue[2]);
+    }
+  } else {
+    return;
+  }
+  for (int c = 0; c < 5; ++c) q[(long long)c * N + id] = qo[c];
+}
+
+// ---------------------------------------------------------------------------------------
+// Time step: dt = CFL min over updated nodes of J^-1 / sum_d Lam_d; block minima, then one
+// block reduces them (min is exact whatever the order).
+// ---------------------------------------------------------------------------------------
+// Minimum over one 64 x 4 block of plane k, written to *slot; red is 256 doubles of LDS.
+__device__ __forceinline__ void dt_block(const Dims& D, const Phys& P, const double* __restrict__ q,
+                                         const double* __restrict__ S,
+                                         const double* __restrict__ jinv, int bx, int by, int k,
+                                         double* __restrict__ slot, int* __restrict__ flag,
+                                         double* red) {
+  const int i = bx * 64 + threadIdx.x, j = by * 4 + threadIdx.y;
+  const int tid = threadIdx.x + 64 * threadIdx.y;
+  double r = INFINITY;
+  if (i < D.n[0] && j < D.n[1] && is_updated(D, i, j, k)) {
+    const int N = (int)D.N;
+    const int id = i + D.n[0] * (j + D.n[1] * k);
+    Prim s = prim_from_q(q[id], q[N + id], q[2 * N + id], q[3 * N + id], q[4 * N + id], P);
+    double a = sqrt(s.T);
+    double l = spectral(S[id], S[N + id], S[2 * N + id], s.u, s.v, s.w, a) +
+               spectral(S[3 * N + id], S[4 * N + id], S[5 * N + id], s.u, s.v, s.w, a) +
+               spectral(S[6 * N + id], S[7 * N + id], S[8 * N + id], s.u, s.v, s.w, a);
+    r = jinv[id] / l;
+    if (!(s.rho > 0.0) || !(s.p > 0.0) || !isfinite(r)) atomicOr(flag, 2);
+  }
+  red[tid] = r;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if (tid < o) red[tid] = fmin(red[tid], red[tid + o]);
+    __syncthreads();
+  }
+  if (tid == 0) *slot = red[0];
+  __syncthreads();
+}
+
+// dt = CFL times the minimum of the block minima (exact in any order).
+__device__ __forceinline__ void dt_final_block(const double* __restrict__ part, int nparts,
+                                               double cfl, double* __restrict__ dt,
+                                               double* red) {
+  double r = INFINITY;
+  for (int b = threadIdx.x; b < nparts; b += 256) r = fmin(r, part[b]);
+  red[threadIdx.x] = r;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if ((int)threadIdx.x < o) red[threadIdx.x] = fmin(red[threadIdx.x], red[threadIdx.x + o]);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) dt[0] = cfl * red[0];
+  __syncthreads();
+}
+
+// Non-finite or non-positive density/pressure at node (i, j, k) sets flag bit 2.
+__device__ __forceinline__ void check_node(const Dims& D, const Phys& P,
+                                           const double* __restrict__ q, int i, int j, int k,
+                                           int* __restrict__ flag) {
+  if (i >= D.n[0] || j >= D.n[1]) return;
+  const int N = (int)D.N;
+  const int id = i + D.n[0] * (j + D.n[1] * k);
+  Prim s = prim_from_q(q[id], q[N + id], q[2 * N + id], q[3 * N + id], q[4 * N + id], P);
+  bool ok = s.rho > 0.0 && s.p > 0.0 && isfinite(s.u) && isfinite(s.v) && isfinite(s.w) &&
+            isfinite(q[4 * N + id]);
+  if (!ok) atomicOr(flag, 2);
+}
+
+}  // namespace lesmi

@@ -44,4 +44,29 @@ extern const char* const kTileNames[kNumTiles];
 hipError_t launch_nodes(const StageArgs& A, hipStream_t s);
 hipError_t launch_stage(const StageArgs& A, hipStream_t s);
 
+// Thread-tile extent of a tile index, and the z-chunk depth the stage launch uses for it.
+void tile_shape(int tile, int* tx, int* ty);
+int kchunk_for(const Dims& D, int tx, int ty, int kmin);
+
+// A persistent launch over a batch: `args` holds one StageArgs per member (device), `work`
+// the work items (device). grid <= 0 asks for the kernel's resident blocks per CU instead
+// (written to *occupancy).
+struct BatchLaunch {
+  const StageArgs* args;
+  const int4* work;
+  int nwork;
+  int grid;
+  int tile;
+  bool mixed;
+  int* occupancy;
+};
+hipError_t launch_nodes_batch(const BatchLaunch& B, hipStream_t s);
+
+// Stage arguments of a context for input state q (lesmi.hip).
+StageArgs stage_args_of(les_ctx* c, const double* q);
+
+// Runge-Kutta stage coefficients alpha_1..alpha_5 (paper, Time Marching Method).
+constexpr double kAlpha[5] = {0.25, 1.0 / 6.0, 0.375, 0.5, 1.0};
+hipError_t launch_stage_batch(const BatchLaunch& B, hipStream_t s);
+
 }  // namespace lesmi

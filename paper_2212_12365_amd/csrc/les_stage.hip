@@ -67,13 +67,13 @@ __device__ __forceinline__ R w_of(const StageArgs& A, unsigned o, int c, R prel)
 
 // Node record of one node. Primitive variables are formed in FP64 from the FP64 state;
 // the differences, eddy viscosity, spectral radii and sensors are evaluated in R.
+// One 64 x 4 block of nodes at (bx, by) in plane k.
 template <typename R>
-__global__ void __launch_bounds__(256) k_nodes(StageArgs A) {
+__device__ __forceinline__ void nodes_block(const StageArgs& A, int bx, int by, int k) {
   const Dims& D = A.D;
   const PhysT<R> P(A.P);
-  int i = blockIdx.x * blockDim.x + threadIdx.x;
-  int j = blockIdx.y * blockDim.y + threadIdx.y;
-  int k = blockIdx.z;
+  int i = bx * 64 + threadIdx.x;
+  int j = by * 4 + threadIdx.y;
   if (i >= D.n[0] || j >= D.n[1]) return;
   const int N = (int)D.N;
   const double* __restrict__ q = A.q;
@@ -137,6 +137,22 @@ __global__ void __launch_bounds__(256) k_nodes(StageArgs A) {
   r[(kRecNu + 1) * N + o] = nu[1];
   r[(kRecNu + 2) * N + o] = nu[2];
   if (A.mut_out) A.mut_out[o] = (double)mut;
+}
+
+template <typename R>
+__global__ void __launch_bounds__(256) k_nodes(StageArgs A) {
+  nodes_block<R>(A, blockIdx.x, blockIdx.y, blockIdx.z);
+}
+
+// Persistent form over the members of a batch: item = (member, bx, by, k).
+template <typename R>
+__global__ void __launch_bounds__(256) k_nodes_batch(const StageArgs* __restrict__ args,
+                                                     const int4* __restrict__ work, int nwork) {
+  for (int w = blockIdx.x; w < nwork; w += gridDim.x) {
+    const int4 it = work[w];
+    const StageArgs A = args[it.x];
+    nodes_block<R>(A, it.y, it.z, it.w);
+  }
 }
 
 // Maps the dispatch order onto tiles so that each XCD (blocks are dealt round-robin to the
@@ -306,27 +322,21 @@ __device__ __forceinline__ void face_eval(const NA& a, const NB& b, const R* Wm,
 // One block per TX x TY column tile marches a chunk of z-planes (z is periodic). R is the
 // arithmetic type of the fluxes (double; float in the mixed form, where the state, the
 // Runge-Kutta update, J^-1 and J stay FP64).
-template <int TX, int TY, int WPE, typename R>
-__global__ void __launch_bounds__(TX * TY) __attribute__((amdgpu_waves_per_eu(WPE, 8)))
-k_stage_planes(StageArgs A, int kchunk) {
+// Column tile (bx, by) over the z-planes kbeg .. kend-1, with the block's LDS L.
+template <int TX, int TY, typename R>
+__device__ __forceinline__ void stage_block(const StageArgs& A, int bx, int by, int kbeg,
+                                            int kend, PlaneLds<TX, TY, R>& L) {
   using PL = PlaneLds<TX, TY, R>;
   constexpr int NT = TX * TY;
   constexpr int MW = (PL::NW + NT - 1) / NT;  // staging slots per thread
   constexpr int M1 = (PL::N1 + NT - 1) / NT;
   constexpr int MX = (PL::NX + NT - 1) / NT;  // face slots per thread
   constexpr int MY = (PL::NY + NT - 1) / NT;
-  __shared__ PL L;
   const Dims& D = A.D;
   const PhysT<R> Ph(A.P);
   const int N = (int)D.N;
   const int ni = D.n[0], nj = D.n[1], nk = D.n[2];
-  const int gx = gridDim.x, gy = gridDim.y;
-  const int lin = blockIdx.x + gx * (blockIdx.y + gy * blockIdx.z);
-  const int t = xcd_tile(lin, gx * gy * gridDim.z);
-  const int bx = t % gx, by = (t / gx) % gy, bz = t / (gx * gy);
   const int i0 = bx * TX, j0 = by * TY;
-  const int kbeg = bz * kchunk;
-  const int kend = min(kbeg + kchunk, nk);
   const int tid = threadIdx.x;
   const int a = tid % TX, b = tid / TX;
   const int i = i0 + a, j = j0 + b;
@@ -532,6 +542,32 @@ k_stage_planes(StageArgs A, int kchunk) {
   }
 }
 
+template <int TX, int TY, int WPE, typename R>
+__global__ void __launch_bounds__(TX * TY) __attribute__((amdgpu_waves_per_eu(WPE, 8)))
+k_stage_planes(StageArgs A, int kchunk) {
+  __shared__ PlaneLds<TX, TY, R> L;
+  const int gx = gridDim.x, gy = gridDim.y;
+  const int lin = blockIdx.x + gx * (blockIdx.y + gy * blockIdx.z);
+  const int t = xcd_tile(lin, gx * gy * gridDim.z);
+  const int bx = t % gx, by = (t / gx) % gy, bz = t / (gx * gy);
+  const int kbeg = bz * kchunk;
+  stage_block<TX, TY, R>(A, bx, by, kbeg, min(kbeg + kchunk, A.D.n[2]), L);
+}
+
+// Persistent form over the members of a batch: item = (member, bx | by << 16, kbeg, kend).
+// The grid is a multiple of 8 blocks, so block b stays on XCD b % 8 and its items, remapped
+// by xcd_tile, form one contiguous run of the work list per XCD.
+template <int TX, int TY, int WPE, typename R>
+__global__ void __launch_bounds__(TX * TY) __attribute__((amdgpu_waves_per_eu(WPE, 8)))
+k_stage_batch(const StageArgs* __restrict__ args, const int4* __restrict__ work, int nwork) {
+  __shared__ PlaneLds<TX, TY, R> L;
+  for (int w = blockIdx.x; w < nwork; w += gridDim.x) {
+    const int4 it = work[xcd_tile(w, nwork)];
+    const StageArgs A = args[it.x];
+    stage_block<TX, TY, R>(A, it.y & 0xffff, it.y >> 16, it.z, it.w, L);
+  }
+}
+
 }  // namespace
 
 hipError_t launch_nodes(const StageArgs& A, hipStream_t s) {
@@ -550,11 +586,74 @@ const char* const kTileNames[kNumTiles] = {"32x8", "32x4", "16x8", "16x16", "16x
 template <int TX, int TY, int WPE = 1, typename R = double>
 hipError_t launch_planes(const StageArgs& A, hipStream_t s, int kmin) {
   const int gx = (A.D.n[0] + TX - 1) / TX, gy = (A.D.n[1] + TY - 1) / TY;
-  int nz = (1024 + gx * gy - 1) / (gx * gy);
-  nz = max(1, min(nz, A.D.n[2] / kmin));
-  const int kchunk = (A.D.n[2] + nz - 1) / nz;
-  nz = (A.D.n[2] + kchunk - 1) / kchunk;
+  const int kchunk = kchunk_for(A.D, TX, TY, kmin);
+  const int nz = (A.D.n[2] + kchunk - 1) / kchunk;
   hipLaunchKernelGGL((k_stage_planes<TX, TY, WPE, R>), dim3(gx, gy, nz), dim3(TX * TY), 0, s, A, kchunk);
+  return hipGetLastError();
+}
+
+void tile_shape(int tile, int* tx, int* ty) {
+  static const int shapes[kNumTiles][2] = {{32, 8}, {32, 4}, {16, 8}, {16, 16}, {16, 8}, {16, 16}};
+  const int t = tile >= 0 && tile < kNumTiles ? tile : 0;
+  *tx = shapes[t][0];
+  *ty = shapes[t][1];
+}
+
+int kchunk_for(const Dims& D, int tx, int ty, int kmin) {
+  const int gx = (D.n[0] + tx - 1) / tx, gy = (D.n[1] + ty - 1) / ty;
+  int nz = (1024 + gx * gy - 1) / (gx * gy);
+  nz = max(1, min(nz, D.n[2] / max(kmin, 1)));
+  return (D.n[2] + nz - 1) / nz;
+}
+
+namespace {
+
+template <int TX, int TY, int WPE, typename R>
+hipError_t batch_stage(const BatchLaunch& B, hipStream_t s) {
+  auto k = k_stage_batch<TX, TY, WPE, R>;
+  if (B.grid <= 0) {  // occupancy query only
+    int nb = 0;
+    hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k, TX * TY, 0);
+    *B.occupancy = nb;
+    return e;
+  }
+  hipLaunchKernelGGL(k, dim3(B.grid), dim3(TX * TY), 0, s, B.args, B.work, B.nwork);
+  return hipGetLastError();
+}
+
+template <typename R>
+hipError_t batch_stage_tile(const BatchLaunch& B, hipStream_t s) {
+  switch (B.tile) {
+    case 1: return batch_stage<32, 4, 1, R>(B, s);
+    case 2: return batch_stage<16, 8, 1, R>(B, s);
+    case 3: return batch_stage<16, 16, 1, R>(B, s);
+    case 4: return batch_stage<16, 8, 2, R>(B, s);
+    case 5: return batch_stage<16, 16, 2, R>(B, s);
+    default: return batch_stage<32, 8, 1, R>(B, s);
+  }
+}
+
+}  // namespace
+
+hipError_t launch_stage_batch(const BatchLaunch& B, hipStream_t s) {
+  return B.mixed ? batch_stage_tile<float>(B, s) : batch_stage_tile<double>(B, s);
+}
+
+hipError_t launch_nodes_batch(const BatchLaunch& B, hipStream_t s) {
+  if (B.grid <= 0) {
+    int nb = 0;
+    hipError_t e = B.mixed
+        ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_nodes_batch<float>, 256, 0)
+        : hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_nodes_batch<double>, 256, 0);
+    *B.occupancy = nb;
+    return e;
+  }
+  if (B.mixed)
+    hipLaunchKernelGGL(k_nodes_batch<float>, dim3(B.grid), dim3(64, 4), 0, s, B.args, B.work,
+                       B.nwork);
+  else
+    hipLaunchKernelGGL(k_nodes_batch<double>, dim3(B.grid), dim3(64, 4), 0, s, B.args, B.work,
+                       B.nwork);
   return hipGetLastError();
 }
 

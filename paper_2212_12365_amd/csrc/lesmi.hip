@@ -10,6 +10,7 @@
 #include <new>
 #include <vector>
 
+#include "les_bcdt.h"
 #include "les_common.h"
 #include "les_stage.h"
 
@@ -171,231 +172,41 @@ __global__ void k_bc_normals(Dims D, const double* __restrict__ S, BcData B) {
 }
 
 // ---------------------------------------------------------------------------------------
-// Boundary conditions (paper, Boundary Conditions).
+// Boundary conditions, time step and state check (bodies in les_bcdt.h).
 // ---------------------------------------------------------------------------------------
-
-// Far-field Riemann state from the interior state qe and the unit outward normal n.
-__device__ void farfield_state(const Phys& P, const BcData& B, const double* qe,
-                               const double* n, double* qo) {
-  double g = P.gamma;
-  double re = qe[0];
-  double ue[3] = {qe[1] / re, qe[2] / re, qe[3] / re};
-  double pe = P.gm1 * (qe[4] - 0.5 * re * (ue[0] * ue[0] + ue[1] * ue[1] + ue[2] * ue[2]));
-  double ae = sqrt(g * pe / re);
-  double ainf = sqrt(g * B.p_inf / B.rho_inf);
-  double qne = ue[0] * n[0] + ue[1] * n[1] + ue[2] * n[2];
-  double qninf = B.u_inf[0] * n[0] + B.u_inf[1] * n[1] + B.u_inf[2] * n[2];
-  double rp = qne + 2.0 * ae * P.inv_gm1;
-  double rm = qninf - 2.0 * ainf * P.inv_gm1;
-  double qnf = 0.5 * (rp + rm);
-  double af = 0.25 * P.gm1 * (rp - rm);
-  double mn = qne / ae;
-  double uf[3], rf, pf;
-  if (mn >= 1.0) {
-    for (int c = 0; c < 5; ++c) qo[c] = qe[c];
-    return;
-  } else if (mn >= 0.0) {
-    for (int c = 0; c < 3; ++c) uf[c] = ue[c] + (qnf - qne) * n[c];
-    rf = pow(pow(re, g) * af * af / (g * pe), P.inv_gm1);
-    pf = rf * af * af / g;
-  } else if (mn > -1.0) {
-    for (int c = 0; c < 3; ++c) uf[c] = B.u_inf[c] + (qnf - qninf) * n[c];
-    rf = pow(pow(B.rho_inf, g) * af * af / (g * B.p_inf), P.inv_gm1);
-    pf = rf * af * af / g;
-  } else {
-    for (int c = 0; c < 3; ++c) uf[c] = B.u_inf[c];
-    rf = B.rho_inf;
-    pf = B.p_inf;
-  }
-  qo[0] = rf;
-  qo[1] = rf * uf[0];
-  qo[2] = rf * uf[1];
-  qo[3] = rf * uf[2];
-  qo[4] = pf * P.inv_gm1 + 0.5 * rf * (uf[0] * uf[0] + uf[1] * uf[1] + uf[2] * uf[2]);
-}
-
-// Centreline means of the first ring, summed in k order (paper, Centerline Boundary
-// Condition). One block per axial station i: the ring is staged through LDS in chunks and
-// five threads add it up sequentially, so the sum order is k = 0, 1, ..., nk-1.
-constexpr int kAxisChunk = 1024;
 __global__ void __launch_bounds__(256) k_axis_mean(Dims D, const double* __restrict__ q,
                                                    double* __restrict__ axis) {
   __shared__ double ring[5][kAxisChunk];
-  const int i = blockIdx.x + 1;  // 1 <= i <= ni - 2
-  const long long N = D.N;
-  const int nk = D.n[2];
-  double sum = 0.0;  // thread c < 5 accumulates component c
-  for (int kb = 0; kb < nk; kb += kAxisChunk) {
-    int len = min(kAxisChunk, nk - kb);
-    for (int t = threadIdx.x; t < 5 * len; t += blockDim.x) {
-      int c = t / len, k = kb + t % len;
-      ring[c][k - kb] = q[(long long)c * N + nid(D, i, 1, k)];
-    }
-    __syncthreads();
-    if (threadIdx.x < 5)
-      for (int k = 0; k < len; ++k) sum += ring[threadIdx.x][k];
-    __syncthreads();
-  }
-  if (threadIdx.x < 5) axis[(long long)threadIdx.x * D.n[0] + i] = sum / (double)nk;
+  axis_mean_block(D, q, axis, blockIdx.x + 1, ring);
 }
 
-__device__ __forceinline__ void load_q(const double* q, long long N, long long id, double* o) {
-  for (int c = 0; c < 5; ++c) o[c] = q[(long long)c * N + id];
-}
-
-// One thread per boundary node. Far field (j = nj-1, 1 <= i <= ni-2), centreline (j = 0,
-// 1 <= i <= ni-2), entrance (i = 0), exit (i = ni-1). Each boundary value is composed from
-// updated nodes only, reproducing the order far field -> centreline -> entrance -> exit.
 __global__ void k_bc(Dims D, Phys P, BcData B, double* __restrict__ q) {
-  int ni = D.n[0], nj = D.n[1], nk = D.n[2];
-  long long N = D.N;
-  long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  long long nrow = (long long)(ni - 2) * nk;
-  long long nface = (long long)nj * nk;
-  double qe[5], qo[5], n[3];
-  auto ff_normal = [&](int i, int k, double* o) {
-    long long s = (long long)ni * nk, off = i + (long long)ni * k;
-    o[0] = B.nff[off];
-    o[1] = B.nff[s + off];
-    o[2] = B.nff[2 * s + off];
-  };
-  // Far-field state of node (i, nj-1, k), from its interior neighbour.
-  auto farfield_node = [&](int i, int k, double* o) {
-    double qi[5], nn[3];
-    load_q(q, N, nid(D, i, nj - 2, k), qi);
-    ff_normal(i, k, nn);
-    farfield_state(P, B, qi, nn, o);
-  };
-  // State of node (i, j, k) after the far field and centreline conditions.
-  auto after_j = [&](int i, int j, int k, double* o) {
-    if (j == nj - 1)
-      farfield_node(i, k, o);
-    else if (j == 0)
-      for (int c = 0; c < 5; ++c) o[c] = B.axis[(long long)c * ni + i];
-    else
-      load_q(q, N, nid(D, i, j, k), o);
-  };
-  long long id;
-  if (t < nrow) {  // far field
-    int i = 1 + (int)(t % (ni - 2)), k = (int)(t / (ni - 2));
-    farfield_node(i, k, qo);
-    id = nid(D, i, nj - 1, k);
-  } else if (t < 2 * nrow) {  // centreline
-    long long o = t - nrow;
-    int i = 1 + (int)(o % (ni - 2)), k = (int)(o / (ni - 2));
-    for (int c = 0; c < 5; ++c) qo[c] = B.axis[(long long)c * ni + i];
-    id = nid(D, i, 0, k);
-  } else if (t < 2 * nrow + nface) {  // entrance
-    long long o = t - 2 * nrow;
-    int j = (int)(o % nj), k = (int)(o / nj);
-    id = nid(D, 0, j, k);
-    if (B.jetmask[o]) {
-      double uj = B.mach_jet;
-      qo[0] = 1.0;
-      qo[1] = uj;
-      qo[2] = 0.0;
-      qo[3] = 0.0;
-      qo[4] = (1.0 / P.gamma) * P.inv_gm1 + 0.5 * uj * uj;
-    } else {
-      after_j(1, j, k, qe);
-      n[0] = B.nin[o];
-      n[1] = B.nin[nface + o];
-      n[2] = B.nin[2 * nface + o];
-      farfield_state(P, B, qe, n, qo);
-    }
-  } else if (t < 2 * nrow + 2 * nface) {  // exit
-    long long o = t - 2 * nrow - nface;
-    int j = (int)(o % nj), k = (int)(o / nj);
-    id = nid(D, ni - 1, j, k);
-    after_j(ni - 2, j, k, qe);
-    n[0] = B.nex[o];
-    n[1] = B.nex[nface + o];
-    n[2] = B.nex[2 * nface + o];
-    double re = qe[0];
-    double ue[3] = {qe[1] / re, qe[2] / re, qe[3] / re};
-    double pe = P.gm1 * (qe[4] - 0.5 * re * (ue[0] * ue[0] + ue[1] * ue[1] + ue[2] * ue[2]));
-    double ae = sqrt(P.gamma * pe / re);
-    double mn = (ue[0] * n[0] + ue[1] * n[1] + ue[2] * n[2]) / ae;
-    if (mn >= 1.0) {
-      for (int c = 0; c < 5; ++c) qo[c] = qe[c];
-    } else {
-      double eint = pe / (P.gm1 * re);
-      double rb = B.p_inf / (P.gm1 * eint);
-      qo[0] = rb;
-      qo[1] = rb * ue[0];
-      qo[2] = rb * ue[1];
-      qo[3] = rb * ue[2];
-      qo[4] = B.p_inf * P.inv_gm1 + 0.5 * rb * (ue[0] * ue[0] + ue[1] * ue[1] + ue[2] * ue[2]);
-    }
-  } else {
-    return;
-  }
-  for (int c = 0; c < 5; ++c) q[(long long)c * N + id] = qo[c];
+  bc_node(D, P, B, q, (long long)blockIdx.x * blockDim.x + threadIdx.x);
 }
 
-// ---------------------------------------------------------------------------------------
-// Time step: dt = CFL min over updated nodes of J^-1 / sum_d Lam_d; block minima, then one
-// block reduces them (min is exact whatever the order).
-// ---------------------------------------------------------------------------------------
 __global__ void __launch_bounds__(256) k_dt_partial(Dims D, Phys P, const double* __restrict__ q,
                                                     const double* __restrict__ S,
                                                     const double* __restrict__ jinv,
                                                     double* __restrict__ part,
                                                     int* __restrict__ flag) {
   __shared__ double red[256];
-  const int i = blockIdx.x * 64 + threadIdx.x, j = blockIdx.y * 4 + threadIdx.y, k = blockIdx.z;
-  const int tid = threadIdx.x + 64 * threadIdx.y;
-  double r = INFINITY;
-  if (i < D.n[0] && j < D.n[1] && is_updated(D, i, j, k)) {
-    const int N = (int)D.N;
-    const int id = i + D.n[0] * (j + D.n[1] * k);
-    Prim s = prim_from_q(q[id], q[N + id], q[2 * N + id], q[3 * N + id], q[4 * N + id], P);
-    double a = sqrt(s.T);
-    double l = spectral(S[id], S[N + id], S[2 * N + id], s.u, s.v, s.w, a) +
-               spectral(S[3 * N + id], S[4 * N + id], S[5 * N + id], s.u, s.v, s.w, a) +
-               spectral(S[6 * N + id], S[7 * N + id], S[8 * N + id], s.u, s.v, s.w, a);
-    r = jinv[id] / l;
-    if (!(s.rho > 0.0) || !(s.p > 0.0) || !isfinite(r)) atomicOr(flag, 2);
-  }
-  red[tid] = r;
-  __syncthreads();
-  for (int o = 128; o > 0; o >>= 1) {
-    if (tid < o) red[tid] = fmin(red[tid], red[tid + o]);
-    __syncthreads();
-  }
-  if (tid == 0)
-    part[blockIdx.x + gridDim.x * (blockIdx.y + gridDim.y * blockIdx.z)] = red[0];
+  dt_block(D, P, q, S, jinv, blockIdx.x, blockIdx.y, blockIdx.z,
+           part + blockIdx.x + gridDim.x * (blockIdx.y + gridDim.y * blockIdx.z), flag, red);
 }
 
-// dt = CFL times the minimum of the block minima (exact in any order).
 __global__ void __launch_bounds__(256) k_dt_final(const double* __restrict__ part, int nparts,
                                                   double cfl, double* __restrict__ dt) {
   __shared__ double red[256];
-  double r = INFINITY;
-  for (int b = threadIdx.x; b < nparts; b += 256) r = fmin(r, part[b]);
-  red[threadIdx.x] = r;
-  __syncthreads();
-  for (int o = 128; o > 0; o >>= 1) {
-    if ((int)threadIdx.x < o) red[threadIdx.x] = fmin(red[threadIdx.x], red[threadIdx.x + o]);
-    __syncthreads();
-  }
-  if (threadIdx.x == 0) dt[0] = cfl * red[0];
+  dt_final_block(part, nparts, cfl, dt, red);
 }
 
 __global__ void k_set_scalar(double* p, double v) { p[0] = v; }
 __global__ void k_set_int(int* p, int v) { p[0] = v; }
 
-// Non-finite or non-positive density/pressure anywhere in q sets flag bit 2.
 __global__ void __launch_bounds__(256) k_check(Dims D, Phys P, const double* __restrict__ q,
                                                int* __restrict__ flag) {
-  const int i = blockIdx.x * 64 + threadIdx.x, j = blockIdx.y * 4 + threadIdx.y, k = blockIdx.z;
-  if (i >= D.n[0] || j >= D.n[1]) return;
-  const int N = (int)D.N;
-  const int id = i + D.n[0] * (j + D.n[1] * k);
-  Prim s = prim_from_q(q[id], q[N + id], q[2 * N + id], q[3 * N + id], q[4 * N + id], P);
-  bool ok = s.rho > 0.0 && s.p > 0.0 && isfinite(s.u) && isfinite(s.v) && isfinite(s.w) &&
-            isfinite(q[4 * N + id]);
-  if (!ok) atomicOr(flag, 2);
+  check_node(D, P, q, blockIdx.x * 64 + threadIdx.x, blockIdx.y * 4 + threadIdx.y, blockIdx.z,
+             flag);
 }
 
 // ---------------------------------------------------------------------------------------
@@ -621,6 +432,8 @@ int run_bc(les_ctx* c, double* q, hipStream_t s) {
 
 }  // namespace
 
+StageArgs lesmi::stage_args_of(les_ctx* c, const double* q) { return stage_args(c, q); }
+
 extern "C" {
 
 int les_init_grid(const les_params* params, const double* xyz, les_ctx** out) {
@@ -735,7 +548,6 @@ int les_step(les_ctx* c, double* q, int nsteps, double cfl, double dt_fixed, dou
              void* stream) {
   if (!c || !q || nsteps < 0) return fail(c, LES_EINVAL, "bad argument");
   if (!(cfl > 0.0) && !(dt_fixed > 0.0)) return fail(c, LES_EINVAL, "need cfl > 0 or dt_fixed > 0");
-  static const double alpha[5] = {0.25, 1.0 / 6.0, 0.375, 0.5, 1.0};
   hipStream_t s = (hipStream_t)stream;
   const Dims& D = c->dims;
   hipLaunchKernelGGL(k_set_int, dim3(1), dim3(1), 0, s, c->d_flag, 0);
@@ -752,7 +564,7 @@ int les_step(les_ctx* c, double* q, int nsteps, double cfl, double dt_fixed, dou
     const double* in = q;
     for (int l = 0; l < 5; ++l) {
       double* outb = (l == 4) ? q : ((l % 2 == 0) ? c->qa : c->qb);
-      int rc = run_stage(c, in, 1, outb, q, alpha[l], s);
+      int rc = run_stage(c, in, 1, outb, q, kAlpha[l], s);
       if (rc) return rc;
       rc = run_bc(c, outb, s);
       if (rc) return rc;
@@ -837,6 +649,52 @@ int les_profile_read(les_ctx* c, double* nodes_ms, double* faces_ms, long long* 
   if (faces_ms) *faces_ms = tf;
   *stages = (long long)(c->nrec / 3);
   c->nrec = 0;
+  return LES_OK;
+}
+
+int les_autotune(les_ctx* c, const double* q, int* tile, int* kmin, void* stream) {
+  if (!c || !q) return fail(c, LES_EINVAL, "null argument");
+  hipStream_t s = (hipStream_t)stream;
+  static const int kmins[] = {4, 8, 16};
+  StageArgs A = stage_args(c, q);
+  A.mode = 0;
+  A.out = c->qa;
+  hipEvent_t e0, e1;
+  HIP_TRY(c, hipEventCreate(&e0));
+  HIP_TRY(c, hipEventCreate(&e1));
+  hipError_t err = launch_nodes(A, s);
+  float best = INFINITY;
+  int bt = c->tile, bk = c->kmin;
+  for (int t = 0; err == hipSuccess && t < kNumTiles; ++t)
+    for (int km : kmins) {
+      A.tile = t;
+      A.kmin = km;
+      float ms = INFINITY;
+      for (int rep = 0; rep < 3 && err == hipSuccess; ++rep) {
+        (void)hipEventRecord(e0, s);
+        err = launch_stage(A, s);
+        (void)hipEventRecord(e1, s);
+        if (err == hipSuccess) err = hipEventSynchronize(e1);
+        float x = 0.f;
+        (void)hipEventElapsedTime(&x, e0, e1);
+        if (rep > 0) ms = fminf(ms, x);  // the first launch warms the caches
+      }
+      if (err == hipSuccess && ms < best) {
+        best = ms;
+        bt = t;
+        bk = km;
+      }
+    }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (err != hipSuccess) {
+    c->err = std::string("autotune: ") + hipGetErrorString(err);
+    return LES_EHIP;
+  }
+  c->tile = bt;
+  c->kmin = bk;
+  if (tile) *tile = bt;
+  if (kmin) *kmin = bk;
   return LES_OK;
 }
 

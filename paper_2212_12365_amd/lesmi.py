@@ -73,6 +73,19 @@ def load():
         lib.les_tuning_name.restype = ctypes.c_char_p
         lib.les_profile.argtypes = [vp, ctypes.c_int]
         lib.les_profile_read.argtypes = [vp, dp, dp, ctypes.POINTER(ctypes.c_longlong)]
+        ip = ctypes.POINTER(ctypes.c_int)
+        lib.les_autotune.argtypes = [vp, vp, ip, ip, vp]
+        lib.les_batch_create.argtypes = [ctypes.POINTER(vp), ctypes.c_int, ctypes.POINTER(vp)]
+        lib.les_batch_step.argtypes = [vp, ctypes.POINTER(vp), ctypes.c_int, ctypes.c_double,
+                                       ctypes.c_double, dp, vp]
+        lib.les_batch_set_tuning.argtypes = [vp, ctypes.c_int, ctypes.c_int]
+        lib.les_batch_get_tuning.argtypes = [vp, ip, ip]
+        lib.les_batch_autotune.argtypes = [vp, ctypes.POINTER(vp), ip, ip, vp]
+        lib.les_batch_set_graph.argtypes = [vp, ctypes.c_int]
+        lib.les_batch_destroy.argtypes = [vp]
+        lib.les_batch_destroy.restype = None
+        lib.les_batch_last_error.argtypes = [vp]
+        lib.les_batch_last_error.restype = ctypes.c_char_p
         lib.les_destroy.argtypes = [vp]
         lib.les_destroy.restype = None
         lib.les_last_error.argtypes = [vp]
@@ -215,12 +228,89 @@ class Context:
                                               ctypes.byref(n)), "les_profile_read")
         return tn.value, tf.value, n.value
 
+    def autotune(self, q, stream=None):
+        """Times every stage-kernel launch shape on residuals of q; keeps and returns the
+        fastest (tile, kmin)."""
+        t, k = ctypes.c_int(0), ctypes.c_int(0)
+        self._check(self.lib.les_autotune(self.handle, _dev(q, 5 * self.n, "q"), ctypes.byref(t),
+                                          ctypes.byref(k), _stream(stream)), "les_autotune")
+        return t.value, k.value
+
     def updated_nodes(self):
         return int(self.lib.les_updated_nodes(self.handle))
 
     def close(self):
         if self.handle and self.handle.value:
             self.lib.les_destroy(self.handle)
+            self.handle = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Batch:
+    """Several contexts advanced together (les_batch_create .. les_batch_destroy). The
+    contexts must outlive the batch and are not stepped on their own meanwhile."""
+
+    def __init__(self, contexts):
+        self.lib = load()
+        self.members = list(contexts)
+        n = len(self.members)
+        arr = (ctypes.c_void_p * n)(*[c.handle.value for c in self.members])
+        h = ctypes.c_void_p()
+        rc = self.lib.les_batch_create(arr, n, ctypes.byref(h))
+        self.handle = h
+        if rc != LES_OK:
+            msg = self.lib.les_batch_last_error(h).decode() if h.value else ""
+            self.close()
+            raise LesError(rc, "les_batch_create", msg)
+
+    def _check(self, rc, what):
+        if rc != LES_OK:
+            raise LesError(rc, what, self.lib.les_batch_last_error(self.handle).decode())
+
+    def _states(self, qs):
+        if len(qs) != len(self.members):
+            raise ValueError("one state per member")
+        return (ctypes.c_void_p * len(qs))(*[
+            _dev(q, 5 * c.n, f"q[{i}]").value for i, (q, c) in enumerate(zip(qs, self.members))])
+
+    def step(self, qs, nsteps, cfl=0.5, dt_fixed=0.0, stream=None):
+        """Advances every member in place; returns the members' last time steps."""
+        dts = np.zeros(len(self.members))
+        self._check(self.lib.les_batch_step(self.handle, self._states(qs), int(nsteps),
+                                            float(cfl), float(dt_fixed),
+                                            dts.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                            _stream(stream)), "les_batch_step")
+        return dts
+
+    def autotune(self, qs, stream=None):
+        t, k = ctypes.c_int(0), ctypes.c_int(0)
+        self._check(self.lib.les_batch_autotune(self.handle, self._states(qs), ctypes.byref(t),
+                                                ctypes.byref(k), _stream(stream)),
+                    "les_batch_autotune")
+        return t.value, k.value
+
+    def set_tuning(self, tile, kmin=8):
+        self._check(self.lib.les_batch_set_tuning(self.handle, int(tile), int(kmin)),
+                    "les_batch_set_tuning")
+
+    def get_tuning(self):
+        t, k = ctypes.c_int(0), ctypes.c_int(0)
+        self._check(self.lib.les_batch_get_tuning(self.handle, ctypes.byref(t), ctypes.byref(k)),
+                    "les_batch_get_tuning")
+        return t.value, k.value
+
+    def set_graph(self, enable=True):
+        self._check(self.lib.les_batch_set_graph(self.handle, int(bool(enable))),
+                    "les_batch_set_graph")
+
+    def close(self):
+        if self.handle and self.handle.value:
+            self.lib.les_batch_destroy(self.handle)
             self.handle = ctypes.c_void_p()
 
     def __del__(self):

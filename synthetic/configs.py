@@ -100,6 +100,25 @@ def make_case(name, n=None, seed=0):
     raise ValueError(name)
 
 
+def make_ensemble(precision=1, shapes=None, copies=4):
+    """The batched ensemble: `copies` seeded jet realisations of each grid shape (seeds
+    0, 1, 2, ... in member order, shapes in the given order, each repeated `copies` times).
+    Returns a list of (params, xyz, q)."""
+    shapes = shapes or ENSEMBLE_SHAPES
+    out, seed = [], 0
+    grids = {}
+    for n in shapes:
+        for _ in range(copies):
+            if n not in grids:
+                grids[n] = jet_grid(n)[0]
+            xyz = grids[n]
+            p = jet_params(n, precision=precision)
+            q = jet_field(xyz, gamma=p.gamma, mach_jet=p.mach_jet, u_inf=p.u_inf[0], seed=seed)
+            out.append((p, xyz, q))
+            seed += 1
+    return out
+
+
 __all__ = ["Params", "BC_PERIODIC", "BC_AXIS", "BC_JET_INFLOW", "BC_FARFIELD", "BC_EXIT",
-           "tgv_params", "jet_params", "box_params", "make_case", "ENSEMBLE_SHAPES",
-           "SUTHERLAND_S1"]
+           "tgv_params", "jet_params", "box_params", "make_case", "make_ensemble",
+           "ENSEMBLE_SHAPES", "SUTHERLAND_S1"]

@@ -1,0 +1,197 @@
+"""Batched ensembles on the GPU through the C ABI (les_batch_*).
+
+* Each member of a batch, stepped by the persistent batch kernels (graph replay or eager
+  launches), equals bitwise its own single-context les_step run: the same device
+  functions evaluate every node and face in the same order, and every member keeps its own
+  CFL time step.
+* A small FP64 batch also matches the FP64 oracle member by member (relative L2 <= 1e-12).
+* Graph replays are checked on several calls in a row with unrelated eager GPU work and
+  synchronisations between them.
+* The autotuners leave the state untouched and pick a valid launch shape.
+* The full 16-member ensemble (4 x 64^3, 4 x 96x64x64, 4 x 128x96x96, 4 x 160x96x96,
+  mixed precision) equals its 16 single-context runs.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import synthetic as sy
+from gpu_cases import case, rel_l2
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch as t
+    assert t.cuda.is_available()
+    return t
+
+
+def _announce(what):
+    print(f"[gpu] {what}", flush=True)
+
+
+SMALL = [(37, 21, 12), (40, 24, 16), (64, 48, 32)]
+
+
+def _members(precision, shapes=SMALL, copies=1, with_box=False):
+    ms = sy.make_ensemble(precision=precision, shapes=shapes, copies=copies)
+    if with_box:
+        p, xyz, q = case("skew24")
+        ms.append((p.replace(precision=precision), xyz, q))
+    return ms
+
+
+def _prepare(torch, members):
+    from paper_2212_12365_amd.lesmi import Context
+    ctxs, states = [], []
+    for p, xyz, q in members:
+        c = Context(p, xyz)
+        g = torch.from_numpy(q).cuda()
+        c.apply_bc(g)
+        ctxs.append(c)
+        states.append(g)
+    return ctxs, states
+
+
+def _single_runs(torch, members, nsteps, calls=1, cfl=0.5):
+    from paper_2212_12365_amd.lesmi import Context
+    out, dts = [], []
+    for p, xyz, q in members:
+        c = Context(p, xyz)
+        g = torch.from_numpy(q).cuda()
+        c.apply_bc(g)
+        for _ in range(calls):
+            dt = c.step(g, nsteps, cfl=cfl)
+        out.append(g.cpu().numpy())
+        dts.append(dt)
+        c.close()
+    return out, dts
+
+
+@pytest.mark.parametrize("precision,graph", [(0, True), (0, False), (1, True), (1, False)])
+def test_batch_equals_single(torch, precision, graph):
+    _announce(f"batch vs single precision={precision} graph={graph}")
+    from paper_2212_12365_amd.lesmi import Batch
+    members = _members(precision, with_box=True)
+    ref, ref_dt = _single_runs(torch, members, 2, calls=3)
+    ctxs, states = _prepare(torch, members)
+    b = Batch(ctxs)
+    b.set_graph(graph)
+    for call in range(3):
+        dts = b.step(states, 2, cfl=0.5)
+        # unrelated eager work and a synchronisation between graph replays
+        x = torch.ones(1 << 20, device="cuda", dtype=torch.float64)
+        assert float(x.sum().item()) == float(1 << 20)
+        torch.cuda.synchronize()
+    for m, (g, r) in enumerate(zip(states, ref)):
+        assert np.array_equal(g.cpu().numpy(), r), f"member {m}"
+    assert np.array_equal(dts, np.array(ref_dt))
+    b.close()
+    for c in ctxs:
+        c.close()
+
+
+def test_batch_fp64_vs_oracle(torch):
+    _announce("batch fp64 vs oracle")
+    from paper_2212_12365_amd.lesmi import Batch
+    members = _members(0, shapes=[(37, 21, 12), (40, 24, 16)], copies=1)
+    ctxs, states = _prepare(torch, members)
+    b = Batch(ctxs)
+    dts = b.step(states, 3, cfl=0.5)
+    for m, ((p, xyz, q), g) in enumerate(zip(members, states)):
+        o = oracle.Oracle(p, xyz)
+        ref, dt_ref = o.step(o.apply_bc(q), 3, cfl=0.5)
+        assert dts[m] == pytest.approx(dt_ref, rel=1e-12)
+        err = rel_l2(g.cpu().numpy(), ref)
+        assert np.all(err <= 1e-12), (m, err)
+    b.close()
+
+
+def test_batch_fixed_dt_and_tuning(torch):
+    _announce("batch fixed dt and explicit tunings")
+    from paper_2212_12365_amd.lesmi import Batch, Context
+    members = _members(1)
+    ctxs, states = _prepare(torch, members)
+    ref = []
+    for p, xyz, q in members:
+        c = Context(p, xyz)
+        g = torch.from_numpy(q).cuda()
+        c.apply_bc(g)
+        c.step(g, 2, cfl=0.0, dt_fixed=2e-3)
+        ref.append(g.cpu().numpy())
+        c.close()
+    b = Batch(ctxs)
+    start = [s.clone() for s in states]
+    for tile in range(6):
+        for kmin in (1, 5):
+            for s, s0 in zip(states, start):
+                s.copy_(s0)
+            b.set_tuning(tile, kmin)
+            assert b.get_tuning() == (tile, kmin)
+            dts = b.step(states, 2, cfl=0.0, dt_fixed=2e-3)
+            assert np.all(dts == 2e-3)
+            for m, (g, r) in enumerate(zip(states, ref)):
+                assert np.array_equal(g.cpu().numpy(), r), (tile, kmin, m)
+    b.close()
+
+
+def test_autotuners_keep_state(torch):
+    _announce("autotuners")
+    from paper_2212_12365_amd.lesmi import Batch
+    members = _members(1)
+    ctxs, states = _prepare(torch, members)
+    before = [s.cpu().numpy() for s in states]
+    t, k = ctxs[2].autotune(states[2])
+    assert 0 <= t < 6 and k in (4, 8, 16)
+    b = Batch(ctxs)
+    t, k = b.autotune(states)
+    assert 0 <= t < 6 and k in (4, 8, 16)
+    assert b.get_tuning() == (t, k)
+    for s, s0 in zip(states, before):
+        assert np.array_equal(s.cpu().numpy(), s0)
+    ref, _ = _single_runs(torch, members, 2)
+    b.step(states, 2, cfl=0.5)
+    for g, r in zip(states, ref):
+        assert np.array_equal(g.cpu().numpy(), r)
+    b.close()
+
+
+def test_batch_errors(torch):
+    _announce("batch error paths")
+    from paper_2212_12365_amd.lesmi import Batch, LesError, LES_EINVAL, LES_ENONFINITE, Context
+    m64 = _members(0)
+    m32 = _members(1)
+    ctxs, states = _prepare(torch, m64)
+    c32 = Context(*m32[0][:2])
+    with pytest.raises(LesError) as e:
+        Batch([ctxs[0], c32])          # mixed precisions in one batch
+    assert e.value.code == LES_EINVAL
+    with pytest.raises(LesError) as e:
+        Batch([ctxs[0], ctxs[0]])      # the same member twice
+    assert e.value.code == LES_EINVAL
+    b = Batch(ctxs)
+    q = states[1].cpu().numpy()
+    q[0, 3, 4, 5] = np.nan
+    states[1].copy_(torch.from_numpy(q))
+    with pytest.raises(LesError) as e:
+        b.step(states, 1, cfl=0.5)
+    assert e.value.code == LES_ENONFINITE
+    assert "member(s) 1" in str(e.value)
+    b.close()
+
+
+def test_full_ensemble_equals_single(torch):
+    _announce("full 16-member ensemble mixed")
+    from paper_2212_12365_amd.lesmi import Batch
+    members = sy.make_ensemble(precision=1)
+    assert len(members) == 16
+    ref, ref_dt = _single_runs(torch, members, 2)
+    ctxs, states = _prepare(torch, members)
+    b = Batch(ctxs)
+    dts = b.step(states, 2, cfl=0.5)
+    for m, (g, r) in enumerate(zip(states, ref)):
+        assert np.array_equal(g.cpu().numpy(), r), f"member {m}"
+    assert np.array_equal(dts, np.array(ref_dt))
+    b.close()
