@@ -6,8 +6,9 @@ kernels each, boundary conditions) of the synthetic M = 1.4 jet on the 256 x 128
 curvilinear grid in FP64, with the state resident in HBM. The JSON line reports
 Mcell-RKstage/s (updated nodes x 5 stages x steps / wall time), the roofline position of the
 dominant kernel (the face kernel, timed live with HIP events on the stream it runs on), the
-same workload in the mixed-precision form, and the CPU oracle timed on a bounded sample of
-the same workload.
+same workload in the mixed-precision form, the 16-member batched ensemble against the same
+members run one after another, and the CPU oracle timed on a bounded sample of the same
+workload.
 """
 import argparse
 import hashlib
@@ -89,6 +90,53 @@ def run_form(torch, params, xyz, q, steps, warmup):
             "stages": stages, "rate": upd * 5 * steps / wall / 1e6}
 
 
+def run_batched(torch, steps, warmup):
+    """The 16-member mixed-precision ensemble: one after another through les_step, then as
+    one batch (persistent launches, graph-replayed steps, autotuned launch shape)."""
+    import synthetic as sy
+    from paper_2212_12365_amd.lesmi import Batch, Context
+    members = sy.make_ensemble(precision=1)
+    ctxs, states = [], []
+    for p, xyz, q in members:
+        c = Context(p, xyz)
+        g = torch.from_numpy(q).to("cuda")
+        c.apply_bc(g)
+        ctxs.append(c)
+        states.append(g)
+    upd = sum(c.updated_nodes() for c in ctxs)
+    start = [s.clone() for s in states]
+    for c, g in zip(ctxs, states):
+        c.step(g, warmup, cfl=0.5)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for c, g in zip(ctxs, states):
+        c.step(g, steps, cfl=0.5)
+    torch.cuda.synchronize()
+    t_seq = time.perf_counter() - t0
+    for g, g0 in zip(states, start):
+        g.copy_(g0)
+    b = Batch(ctxs)
+    tile, kmin = b.autotune(states)
+    b.step(states, warmup, cfl=0.5)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    b.step(states, steps, cfl=0.5)
+    torch.cuda.synchronize()
+    t_b = time.perf_counter() - t0
+    b.close()
+    for c in ctxs:
+        c.close()
+    bm = BYTES_PER_CELL_STAGE["mixed"]
+    rate = upd * 5 * steps / t_b / 1e6
+    return {"value": round(rate, 3), "steps": steps,
+            "members": "4x64x64x64, 4x96x64x64, 4x128x96x96, 4x160x96x96 jets, mixed, seeds 0-15",
+            "updated_nodes": upd, "ms_per_step": round(t_b * 1e3 / steps, 4),
+            "hbm_roofline_pct": round(100 * rate * 1e6 * bm / (HBM_PEAK_GBS * 1e9), 2),
+            "tuning": {"tile": tile, "kmin": kmin},
+            "sequential_value": round(upd * 5 * steps / t_seq / 1e6, 3),
+            "speedup_vs_sequential": round(t_seq / t_b, 3)}
+
+
 def copy_calibration(gib=1.0, reps=5):
     """A plain device copy of known size, for scaling HBM counter readings."""
     import torch
@@ -108,7 +156,9 @@ def main():
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--no-forms", dest="forms", action="store_false",
-                    help="time the FP64 form only (skip the mixed-precision run)")
+                    help="time the FP64 form only (skip the mixed-precision and batched runs)")
+    ap.add_argument("--batch-steps", type=int, default=50,
+                    help="RK steps timed for the batched ensemble and its sequential baseline")
     ap.add_argument("--cpu-steps", type=int, default=15,
                     help="RK steps of the oracle timed for the CPU baseline (0 = skip)")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -154,6 +204,8 @@ def main():
             "face_kernel_us": round(mx["faces_ms"] * 1e3 / max(mx["stages"], 1), 2),
             "node_kernel_us": round(mx["nodes_ms"] * 1e3 / max(mx["stages"], 1), 2),
             "speedup_vs_fp64": round(mx["rate"] / value, 3)}
+    if args.forms:
+        forms["batched"] = run_batched(torch, args.batch_steps, 2)
     out = {
         "metric": "Mcell-RKstage updates/s and % HBM roofline, FP64 vs mixed vs batched",
         "value": round(value, 3),
