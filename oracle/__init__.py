@@ -60,6 +60,7 @@ def _load():
         lib.or_metrics.argtypes = [pp, dp, dp, dp]
         lib.or_sutherland.argtypes = [pp, ctypes.c_int, dp, dp]
         lib.or_sgs_viscosity.argtypes = [pp, dp, dp, dp, dp]
+        lib.or_velocity_gradient.argtypes = [pp, dp, dp, dp, dp]
         lib.or_residual.argtypes = [pp, dp, dp, dp, dp]
         lib.or_apply_bc.argtypes = [pp, dp, dp, dp, dp]
         lib.or_dt.argtypes = [pp, dp, dp, dp, ctypes.c_double, dp]
@@ -134,6 +135,14 @@ class Oracle:
         _check(self.lib.or_sgs_viscosity(ctypes.byref(self.s), _ptr(self.S), _ptr(self.jinv),
                                          _ptr(q), _ptr(mut)), "sgs_viscosity")
         return mut
+
+    def velocity_gradient(self, q):
+        """d u_m / d x_n at every node, shaped (3, 3, nk, nj, ni)."""
+        q = np.ascontiguousarray(q, dtype=np.float64)
+        g = np.zeros((9,) + self.p.shape)
+        _check(self.lib.or_velocity_gradient(ctypes.byref(self.s), _ptr(self.S), _ptr(self.jinv),
+                                             _ptr(q), _ptr(g)), "velocity_gradient")
+        return g.reshape((3, 3) + self.p.shape)
 
     def apply_bc(self, q):
         q = np.array(q, dtype=np.float64, order="C", copy=True)

@@ -577,6 +577,34 @@ int or_sgs_viscosity(const or_params* P, const double* S, const double* jinv, co
   return OR_OK;
 }
 
+/* Velocity gradient g[3m + n] = d u_m / d x_n = J sum_e S_e^n delta_e u_m at every node,
+ * from the same nodal differences as the Smagorinsky viscosity (paper, Subgrid Scale
+ * Viscosity: the strain rate of the resolved field); 0 where J^-1 <= 0. */
+int or_velocity_gradient(const or_params* P, const double* S, const double* jinv,
+                         const double* q, double* grad) {
+  Grid G;
+  int rc = setup(&G, P);
+  if (rc) return rc;
+  Work W;
+  if (work_alloc(&W, G.N)) return OR_ENOMEM;
+  primitives(&G, q, &W);
+  node_differences(&G, &W);
+  long N = G.N;
+#pragma omp parallel for
+  for (int k = 0; k < G.n[2]; ++k)
+    for (long id = (long)k * G.n[0] * G.n[1]; id < (long)(k + 1) * G.n[0] * G.n[1]; ++id) {
+      double J = jinv[id] > 0.0 ? 1.0 / jinv[id] : 0.0;
+      for (int m = 0; m < 3; ++m)
+        for (int n = 0; n < 3; ++n) {
+          double s = 0.0;
+          for (int e = 0; e < 3; ++e) s += S[(long)(3 * e + n) * N + id] * W.dq[e][m][id];
+          grad[(long)(3 * m + n) * N + id] = J * s;
+        }
+    }
+  work_free(&W);
+  return OR_OK;
+}
+
 /* ---------------------------------------------------------------------------------------
  * Boundary conditions (paper, Boundary Conditions).
  * ------------------------------------------------------------------------------------- */

@@ -41,6 +41,9 @@ int or_metrics(const or_params* P, const double* xyz, double* S, double* jinv);
 int or_sutherland(const or_params* P, int n, const double* T, double* mu);
 int or_sgs_viscosity(const or_params* P, const double* S, const double* jinv,
                      const double* q, double* mu_t);
+/* grad [9][N]: d u_m / d x_n at index 3m + n (0 where J^-1 <= 0). */
+int or_velocity_gradient(const or_params* P, const double* S, const double* jinv,
+                         const double* q, double* grad);
 int or_residual(const or_params* P, const double* S, const double* jinv, const double* q,
                 double* rhs);
 int or_apply_bc(const or_params* P, const double* xyz, const double* S, const double* jinv,
