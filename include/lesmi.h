@@ -15,8 +15,8 @@
  *
  * Ownership. The caller owns every array passed in; the context owns the grid metrics,
  * the Runge-Kutta stage buffers, the boundary data and the time-step scalar. Device memory
- * is allocated or freed only by les_init_grid, les_destroy and the batch calls
- * les_batch_create, les_batch_set_tuning, les_batch_autotune and les_batch_destroy.
+ * is allocated or freed only by les_init_grid, les_destroy, les_mlp_fit_norm and the batch
+ * calls les_batch_create, les_batch_set_tuning, les_batch_autotune and les_batch_destroy.
  *
  * Streams. `stream` is a hipStream_t (NULL = the null stream). Every call except
  * les_init_grid and les_destroy is asynchronous on that stream, and may be issued from
@@ -55,6 +55,26 @@ typedef enum {
 
 typedef enum { LES_FP64 = 0, LES_MIXED = 1 } les_precision;
 typedef enum { LES_SMAGORINSKY = 0, LES_MLP = 1 } les_closure;
+
+/* Learned subgrid closure (closure = LES_MLP). The paper's eddy-viscosity form
+ * mu_t = rho c Delta^2 |S| (Subgrid Scale Modeling) with the coefficient c predicted per
+ * node by a 6-64-64-1 network from six scale-free invariants of the resolved velocity
+ * gradient A (S = sym A, O = skew A, S^d its deviatoric part, |S| = (2 S:S)^(1/2)):
+ *   f = (tr S/|S|, tr(S^d S^d)/|S|^2, tr(O O)/|S|^2, tr(S^d S^d S^d)/|S|^3,
+ *        tr(S^d O O)/|S|^3, tr(S^d S^d O O)/|S|^4),
+ *   x = (f - mean) inv_std, h1 = gelu(W1 x + b1), h2 = gelu(W2 h1 + b2),
+ *   c = softplus(w3 . h2 + b3)   (gelu in its tanh form).
+ * Where |S| = 0, an input is not finite or lies outside [lo, hi], c = C_s^2 (plain
+ * Smagorinsky). Parameters are FP32, LES_MLP_NPARAMS values in the order
+ * W1[64][6], b1[64], W2[64][64], b2[64], w3[64], b3; the products run in BF16 with FP32
+ * accumulation. */
+#define LES_MLP_INPUTS 6
+#define LES_MLP_HIDDEN 64
+#define LES_MLP_NPARAMS 4673
+typedef struct {
+  float mean[LES_MLP_INPUTS], inv_std[LES_MLP_INPUTS];  /* input normalisation */
+  float lo[LES_MLP_INPUTS], hi[LES_MLP_INPUTS];         /* trained input range */
+} les_mlp_norm;
 
 /* Problem parameters (paper: Dimensionless Formulation, LES formulation, Subgrid Scale
  * Modeling, Spatial Discretization, Boundary Conditions). Supported boundary sets:
@@ -151,6 +171,62 @@ int les_autotune(les_ctx* ctx, const double* q, int* tile, int* kmin, void* stre
 void les_destroy(les_ctx* ctx);
 
 /* ---------------------------------------------------------------------------------------
+ * Learned closure entry points (layout and fallback rule above).
+ * ------------------------------------------------------------------------------------- */
+
+/* Installs the network of an LES_MLP context: theta DEVICE [LES_MLP_NPARAMS] (copied),
+ * norm HOST. Until it is called, stepping or evaluating an LES_MLP context returns
+ * LES_ESTATE. Synchronous. */
+int les_mlp_set_network(les_ctx* ctx, const float* theta, const les_mlp_norm* norm);
+
+/* Number of node evaluations that fell back to C_s^2 since the last call (resets it).
+ * Synchronous. */
+int les_mlp_fallback_count(les_ctx* ctx, unsigned long long* count);
+
+/* Network inputs of a state: feat DEVICE [6][N] (FP32), smag DEVICE [N] = |S| (FP32). */
+int les_mlp_features(les_ctx* ctx, const double* q, float* feat, float* smag, void* stream);
+
+/* Coefficient c (DEVICE [n]) of n samples with inputs feat DEVICE [6][n] and |S| smag
+ * DEVICE [n], by the network theta DEVICE with normalisation norm HOST; fallback DEVICE
+ * (may be NULL) is incremented by the number of samples that took c = cs2. */
+int les_mlp_coefficient(const float* theta, const les_mlp_norm* norm, float cs2,
+                        const float* feat, const float* smag, long long n, float* c,
+                        unsigned* fallback, void* stream);
+
+/* Training: the loss sum_s w (c_s - y_s)^2 * inv_wsum over the samples idx[0..n-1]
+ * (DEVICE int32 node numbers into feat [6][nfeat], target [nfeat], weight [nfeat]) and its
+ * gradient grad DEVICE [LES_MLP_NPARAMS]; loss DEVICE [1] may be NULL. work DEVICE holds
+ * les_mlp_work_size(n) floats (per-wave partial gradients, summed in a fixed order). */
+long long les_mlp_work_size(long long n);
+int les_mlp_loss_grad(const float* theta, const les_mlp_norm* norm, const float* feat,
+                      long long nfeat, const float* target, const float* weight, const int* idx,
+                      long long n, float inv_wsum, float* grad, float* loss, float* work,
+                      void* stream);
+
+/* One Adam step (Kingma & Ba) on theta with moments m, v (all DEVICE
+ * [LES_MLP_NPARAMS]); step counts from 1. */
+int les_mlp_adam(float* theta, const float* grad, float* m, float* v, int step, float lr,
+                 float beta1, float beta2, float eps, void* stream);
+
+/* Normalisation from the inputs of samples with weight > 0: mean and 1/standard deviation
+ * of each input, and the range [min - widen*span, max + widen*span]. feat DEVICE [6][n],
+ * weight DEVICE [n], out HOST. Allocates a small device buffer; synchronous. */
+int les_mlp_fit_norm(const float* feat, const float* weight, long long n, float widen,
+                     les_mlp_norm* out, void* stream);
+
+/* Training data: box-filters the fine state q_fine (DEVICE [5][Nf], fine context with
+ * exactly twice the coarse nodes per direction) over 2 x 2 x 2 node blocks onto the coarse
+ * grid: q_coarse DEVICE [5][Nc] (block means of the conserved variables) and the subgrid
+ * stress sigma DEVICE [6][Nc] = mean(rho u_m u_n) - rho~ u~_m u~_n (components 00, 11, 22,
+ * 01, 02, 12). On the coarse grid it writes the network inputs feat [6][Nc] and |S~|
+ * smag [Nc] of u~, the least-squares coefficient
+ * target = max(0, -sigma^d : S~^d / (2 rho~ Delta^2 |S~| S~^d : S~^d)), and weight = 1 at
+ * updated nodes with |S~| >= smin, else 0 (all FP32 DEVICE [Nc]). */
+int les_filter_target(les_ctx* fine, les_ctx* coarse, const double* q_fine, float smin,
+                      double* q_coarse, double* sigma, float* feat, float* smag, float* target,
+                      float* weight, void* stream);
+
+/* ---------------------------------------------------------------------------------------
  * Batched ensembles: n independent contexts (for instance seeded jet realisations on grids
  * of different sizes) advanced together. Each kernel of a Runge-Kutta step runs as one
  * persistent launch over a work list spanning every member, and a whole step is captured
@@ -164,8 +240,8 @@ void les_destroy(les_ctx* ctx);
  * ------------------------------------------------------------------------------------- */
 typedef struct les_batch les_batch;
 
-/* members: HOST array of n context handles. On failure *out may still be set so that
- * les_batch_last_error can be read; les_batch_destroy it. */
+/* members: HOST array of n context handles (Smagorinsky closure). On failure *out may
+ * still be set so that les_batch_last_error can be read; les_batch_destroy it. */
 int les_batch_create(les_ctx* const* members, int n, les_batch** out);
 
 /* Advances every member by nsteps steps (as les_step: cfl > 0 gives each member

@@ -61,6 +61,7 @@ def _load():
         lib.or_sutherland.argtypes = [pp, ctypes.c_int, dp, dp]
         lib.or_sgs_viscosity.argtypes = [pp, dp, dp, dp, dp]
         lib.or_velocity_gradient.argtypes = [pp, dp, dp, dp, dp]
+        lib.or_residual_mut.argtypes = [pp, dp, dp, dp, dp, dp]
         lib.or_residual.argtypes = [pp, dp, dp, dp, dp]
         lib.or_apply_bc.argtypes = [pp, dp, dp, dp, dp]
         lib.or_dt.argtypes = [pp, dp, dp, dp, ctypes.c_double, dp]
@@ -127,6 +128,15 @@ class Oracle:
         rhs = np.zeros_like(q)
         _check(self.lib.or_residual(ctypes.byref(self.s), _ptr(self.S), _ptr(self.jinv), _ptr(q),
                                     _ptr(rhs)), "residual")
+        return rhs
+
+    def residual_with_mut(self, q, mu_t):
+        """Residual with the eddy viscosity field mu_t given (shape of the grid)."""
+        q = np.ascontiguousarray(q, dtype=np.float64)
+        mu_t = np.ascontiguousarray(mu_t, dtype=np.float64)
+        rhs = np.zeros_like(q)
+        _check(self.lib.or_residual_mut(ctypes.byref(self.s), _ptr(self.S), _ptr(self.jinv),
+                                        _ptr(q), _ptr(mu_t), _ptr(rhs)), "residual_mut")
         return rhs
 
     def sgs_viscosity(self, q):

@@ -562,6 +562,23 @@ int or_residual(const or_params* P, const double* S, const double* jinv, const d
   return OR_OK;
 }
 
+/* The same residual with a given eddy viscosity mu_t [N] in place of the Smagorinsky value
+ * (for closures that predict the model coefficient). */
+int or_residual_mut(const or_params* P, const double* S, const double* jinv, const double* q,
+                    const double* mu_t, double* rhs) {
+  Grid G;
+  int rc = setup(&G, P);
+  if (rc) return rc;
+  Work W;
+  if (work_alloc(&W, G.N)) return OR_ENOMEM;
+  node_state(&G, S, jinv, q, &W);
+  memcpy(W.mut, mu_t, sizeof(double) * G.N);
+  face_fluxes(&G, S, jinv, q, &W);
+  residual_from_work(&G, &W, rhs);
+  work_free(&W);
+  return OR_OK;
+}
+
 int or_sgs_viscosity(const or_params* P, const double* S, const double* jinv, const double* q,
                      double* mu_t) {
   Grid G;

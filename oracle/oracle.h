@@ -41,6 +41,9 @@ int or_metrics(const or_params* P, const double* xyz, double* S, double* jinv);
 int or_sutherland(const or_params* P, int n, const double* T, double* mu);
 int or_sgs_viscosity(const or_params* P, const double* S, const double* jinv,
                      const double* q, double* mu_t);
+/* Residual with the eddy viscosity mu_t [N] given instead of computed. */
+int or_residual_mut(const or_params* P, const double* S, const double* jinv, const double* q,
+                    const double* mu_t, double* rhs);
 /* grad [9][N]: d u_m / d x_n at index 3m + n (0 where J^-1 <= 0). */
 int or_velocity_gradient(const or_params* P, const double* S, const double* jinv,
                          const double* q, double* grad);

@@ -11,8 +11,8 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "liblesmi.so")
-SOURCES = ["lesmi.hip", "les_stage.hip", "les_batch.hip"]
-HEADERS = ["les_device.h", "les_common.h", "les_stage.h", "les_bcdt.h"]
+SOURCES = ["lesmi.hip", "les_stage.hip", "les_batch.hip", "les_mlp.hip"]
+HEADERS = ["les_device.h", "les_common.h", "les_stage.h", "les_bcdt.h", "les_mlp.h"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",

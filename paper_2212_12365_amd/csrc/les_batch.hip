@@ -379,7 +379,8 @@ int les_batch_create(les_ctx* const* members, int n, les_batch** out) {
   }
   b->mixed = members[0]->params.precision == LES_MIXED;
   for (les_ctx* c : b->m)
-    if ((c->params.precision == LES_MIXED) != b->mixed || c->device != members[0]->device) {
+    if ((c->params.precision == LES_MIXED) != b->mixed || c->device != members[0]->device ||
+        c->params.closure != LES_SMAGORINSKY) {
       delete b;
       return LES_EINVAL;
     }

@@ -76,6 +76,16 @@ struct les_ctx {
   double* d_partial = nullptr;  // [kMaxPartials * 7]
   double* d_diag = nullptr;     // [6]
 
+  // Learned closure (closure == LES_MLP): network parameters (FP32) and input
+  // normalisation, the per-node inputs and scale written by the node kernel, and a count of
+  // nodes where the closure fell back to Smagorinsky.
+  float* mlp_theta = nullptr;
+  les_mlp_norm mlp_norm{};
+  bool mlp_ready = false;
+  float* mlp_feat = nullptr;   // [6][N]
+  float* mlp_scale = nullptr;  // [N]
+  unsigned* mlp_fallback = nullptr;
+
   // Optional timing of the stage kernel launches with HIP events on the caller's stream.
   bool prof = false;
   std::vector<hipEvent_t> ev;

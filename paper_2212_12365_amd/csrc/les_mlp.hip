@@ -1,0 +1,782 @@
+// Learned subgrid closure on gfx950: BF16 MFMA inference and training kernels, Adam, and
+// the box-filter training target (the coefficient form is described in les_mlp.h).
+//
+// Matrix products use v_mfma_f32_16x16x32_bf16 (FP32 accumulate); inference splits each
+// operand into two BF16 parts (three products per matrix product) for about 16 significant
+// bits, training uses plain BF16 products. Fragments, per lane l of a wave (g = l / 16,
+// s = l % 16): A (16 x 32) holds row s, k = 8g .. 8g+7; B (32 x 16) holds column s,
+// k = 8g .. 8g+7; the 16 x 16 result holds column s, rows 4g .. 4g+3.
+// The network is evaluated transposed: hidden units are rows and samples columns, so each
+// lane owns one sample (column s) and, per 16-unit tile, four hidden units 4g .. 4g+3.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <string>
+
+#include "les_common.h"
+#include "les_mlp.h"
+#include "les_stage.h"
+
+using namespace lesmi;
+
+namespace {
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+constexpr int HS = 72;  // LDS stride (bf16) of a sample-major row of 64 hidden values
+constexpr int TS = 40;  // LDS stride (bf16) of a unit-major row of 32 samples
+constexpr float kG0 = 0.7978845608028654f;  // sqrt(2/pi)
+constexpr float kG1 = 0.044715f;
+
+__device__ __forceinline__ f32x4 mfma16(bf16x8 a, bf16x8 b, f32x4 c) {
+  return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
+}
+
+__device__ __forceinline__ float gelu_f(float x) {
+  return 0.5f * x * (1.f + tanhf(kG0 * (x + kG1 * x * x * x)));
+}
+
+__device__ __forceinline__ float gelu_grad_f(float x) {
+  const float t = tanhf(kG0 * (x + kG1 * x * x * x));
+  return 0.5f * (1.f + t) + 0.5f * x * (1.f - t * t) * kG0 * (1.f + 3.f * kG1 * x * x);
+}
+
+__device__ __forceinline__ float softplus_f(float z) {
+  return fmaxf(z, 0.f) + log1pf(expf(-fabsf(z)));
+}
+
+__device__ __forceinline__ float sigmoid_f(float z) { return 0.5f * (1.f + tanhf(0.5f * z)); }
+
+// Split of an FP32 value into two BF16 parts hi + lo (hi = v rounded, lo = the rounded
+// remainder): products of split operands taken as hi*hi + hi*lo + lo*hi carry about 16
+// significant bits instead of 8.
+__device__ __forceinline__ void split_bf16(float v, __bf16& hi, __bf16& lo) {
+  hi = (__bf16)v;
+  lo = (__bf16)(v - (float)hi);
+}
+
+__device__ __forceinline__ void split_frag(const float* v, bf16x8& hi, bf16x8& lo) {
+#pragma unroll
+  for (int i = 0; i < 8; ++i) {
+    __bf16 h, l;
+    split_bf16(v[i], h, l);
+    hi[i] = h;
+    lo[i] = l;
+  }
+}
+
+// Layer-1 A fragment of hidden tile t: W1[16t + s][8g + i] for input index < 6, else 0.
+__device__ __forceinline__ bf16x8 w1_frag(const float* __restrict__ th, int t, int lane) {
+  const int g = lane >> 4, r = 16 * t + (lane & 15);
+  bf16x8 a;
+#pragma unroll
+  for (int i = 0; i < 8; ++i)
+    a[i] = (__bf16)((g == 0 && i < kMlpIn) ? th[kOffW1 + r * kMlpIn + i] : 0.f);
+  return a;
+}
+
+__device__ __forceinline__ void w1_frag_split(const float* __restrict__ th, int t, int lane,
+                                              bf16x8& hi, bf16x8& lo) {
+  const int g = lane >> 4, r = 16 * t + (lane & 15);
+  float v[8];
+#pragma unroll
+  for (int i = 0; i < 8; ++i) v[i] = (g == 0 && i < kMlpIn) ? th[kOffW1 + r * kMlpIn + i] : 0.f;
+  split_frag(v, hi, lo);
+}
+
+__device__ __forceinline__ void w2_frag_split(const float* __restrict__ th, int t, int kb,
+                                              int lane, bf16x8& hi, bf16x8& lo) {
+  const int r = 16 * t + (lane & 15), k0 = 32 * kb + 8 * (lane >> 4);
+  float v[8];
+#pragma unroll
+  for (int i = 0; i < 8; ++i) v[i] = th[kOffW2 + r * kMlpH + k0 + i];
+  split_frag(v, hi, lo);
+}
+
+
+// Normalised inputs x of one sample and whether the network applies there.
+__device__ __forceinline__ bool mlp_input(const MlpNet& net, const float* f, float pos,
+                                          float* x) {
+  bool ok = pos > 0.f && isfinite(pos);
+#pragma unroll
+  for (int c = 0; c < kMlpIn; ++c) {
+    const float v = f[c];
+    const bool fin = isfinite(v);
+    ok = ok && fin && v >= net.norm.lo[c] && v <= net.norm.hi[c];
+    x[c] = ((fin ? v : 0.f) - net.norm.mean[c]) * net.norm.inv_std[c];
+  }
+  return ok;
+}
+
+// Forward pass of the 16 samples of a wave in plain BF16 products (training): sample s in
+// lanes s, s+16, s+32, s+48, inputs x read from lanes 0..15, layer-2 A fragments from the
+// LDS copy W2s [64][HS] of W2; H is the wave's [16][HS] scratch. Returns
+// z (in every lane of the sample) and leaves the pre-activations in a1, a2. The caller
+// guarantees block-uniform control flow (the function synchronises the block).
+__device__ __forceinline__ float forward16(const float* __restrict__ th, const bf16x8 (&w1)[4],
+                                           const __bf16* W2s, const float* x, int lane,
+                                           __bf16* H, f32x4 (&a1)[4], f32x4 (&a2)[4]) {
+  const int g = lane >> 4, s = lane & 15;
+  bf16x8 bx;
+#pragma unroll
+  for (int i = 0; i < 8; ++i) bx[i] = (__bf16)((g == 0 && i < kMlpIn) ? x[i] : 0.f);
+  const f32x4 zero = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+  for (int t = 0; t < 4; ++t) {
+    a1[t] = mfma16(w1[t], bx, zero);
+    bf16x4 h;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      a1[t][i] += th[kOffB1 + 16 * t + 4 * g + i];
+      h[i] = (__bf16)gelu_f(a1[t][i]);
+    }
+    *(bf16x4*)&H[s * HS + 16 * t + 4 * g] = h;
+  }
+  __syncthreads();
+#pragma unroll
+  for (int t = 0; t < 4; ++t) {
+    f32x4 acc = zero;
+#pragma unroll
+    for (int kb = 0; kb < 2; ++kb) {
+      const bf16x8 a = *(const bf16x8*)&W2s[(16 * t + s) * HS + 32 * kb + 8 * g];
+      acc = mfma16(a, *(const bf16x8*)&H[s * HS + 32 * kb + 8 * g], acc);
+    }
+#pragma unroll
+    for (int i = 0; i < 4; ++i) acc[i] += th[kOffB2 + 16 * t + 4 * g + i];
+    a2[t] = acc;
+  }
+  float z = 0.f;
+#pragma unroll
+  for (int t = 0; t < 4; ++t)
+#pragma unroll
+    for (int i = 0; i < 4; ++i) z += th[kOffW3 + 16 * t + 4 * g + i] * gelu_f(a2[t][i]);
+  z += __shfl_xor(z, 16);
+  z += __shfl_xor(z, 32);
+  return z + th[kOffB3];
+}
+
+// The same forward pass with split-BF16 products (three MFMAs per product: hi*hi, hi*lo,
+// lo*hi) for inference: w1h/w1l, w2h/w2l are the split weights, H and Hl the split h1.
+__device__ __forceinline__ float forward16_split(const float* __restrict__ th,
+                                                 const bf16x8 (&w1h)[4], const bf16x8 (&w1l)[4],
+                                                 const bf16x8 (&w2h)[4][2],
+                                                 const bf16x8 (&w2l)[4][2], const float* x,
+                                                 int lane, __bf16* H, __bf16* Hl) {
+  const int g = lane >> 4, s = lane & 15;
+  float xv[8];
+#pragma unroll
+  for (int i = 0; i < 8; ++i) xv[i] = (g == 0 && i < kMlpIn) ? x[i] : 0.f;
+  bf16x8 bxh, bxl;
+  split_frag(xv, bxh, bxl);
+  const f32x4 zero = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+  for (int t = 0; t < 4; ++t) {
+    f32x4 a = mfma16(w1l[t], bxh, zero);
+    a = mfma16(w1h[t], bxl, a);
+    a = mfma16(w1h[t], bxh, a);
+    bf16x4 hh, hl;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      a[i] += th[kOffB1 + 16 * t + 4 * g + i];
+      __bf16 p, q;
+      split_bf16(gelu_f(a[i]), p, q);
+      hh[i] = p;
+      hl[i] = q;
+    }
+    *(bf16x4*)&H[s * HS + 16 * t + 4 * g] = hh;
+    *(bf16x4*)&Hl[s * HS + 16 * t + 4 * g] = hl;
+  }
+  __syncthreads();
+  float z = 0.f;
+#pragma unroll
+  for (int t = 0; t < 4; ++t) {
+    f32x4 acc = zero;
+#pragma unroll
+    for (int kb = 0; kb < 2; ++kb) {
+      const bf16x8 bh = *(const bf16x8*)&H[s * HS + 32 * kb + 8 * g];
+      const bf16x8 bl = *(const bf16x8*)&Hl[s * HS + 32 * kb + 8 * g];
+      acc = mfma16(w2l[t][kb], bh, acc);
+      acc = mfma16(w2h[t][kb], bl, acc);
+      acc = mfma16(w2h[t][kb], bh, acc);
+    }
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+      z += th[kOffW3 + 16 * t + 4 * g + i] * gelu_f(acc[i] + th[kOffB2 + 16 * t + 4 * g + i]);
+  }
+  z += __shfl_xor(z, 16);
+  z += __shfl_xor(z, 32);
+  return z + th[kOffB3];
+}
+
+// ---------------------------------------------------------------------------------------
+// Inference: c per sample, or the closure epilogue mu_t = scale * c into the records.
+// ---------------------------------------------------------------------------------------
+struct InferArgs {
+  MlpNet net;
+  const float* feat;  // [6][n]
+  const float* pos;   // [n]: |S| (or rho Delta^2 |S|); the network applies where > 0
+  long long n;
+  float* c_out;       // [n] or null
+  void* rec;          // closure: mu_t record plane (double, or float if rec_float)
+  int rec_float;
+  double* mut_out;    // optional copy of mu_t
+  unsigned* fallback; // optional count of fallback samples
+};
+
+__global__ void __launch_bounds__(256) k_mlp_infer(InferArgs A) {
+  __shared__ __attribute__((aligned(16))) __bf16 H[4][16 * HS];
+  __shared__ __attribute__((aligned(16))) __bf16 Hl[4][16 * HS];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, g = lane >> 4, s = lane & 15;
+  const float* __restrict__ th = A.net.theta;
+  bf16x8 w1h[4], w1l[4], w2h[4][2], w2l[4][2];
+#pragma unroll
+  for (int t = 0; t < 4; ++t) {
+    w1_frag_split(th, t, lane, w1h[t], w1l[t]);
+    w2_frag_split(th, t, 0, lane, w2h[t][0], w2l[t][0]);
+    w2_frag_split(th, t, 1, lane, w2h[t][1], w2l[t][1]);
+  }
+  unsigned nfb = 0;
+  for (long long base = (long long)blockIdx.x * 64; base < A.n;
+       base += (long long)gridDim.x * 64) {
+    const long long id = base + wv * 16 + s;
+    const bool mine = g == 0 && id < A.n;
+    float x[kMlpIn] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+    float pos = 0.f;
+    bool ok = false;
+    if (mine) {
+      float f[kMlpIn];
+#pragma unroll
+      for (int c = 0; c < kMlpIn; ++c) f[c] = A.feat[c * A.n + id];
+      pos = A.pos[id];
+      ok = mlp_input(A.net, f, pos, x);
+    }
+    const float z = forward16_split(th, w1h, w1l, w2h, w2l, x, lane, H[wv], Hl[wv]);
+    if (mine) {
+      const float c = ok ? softplus_f(z) : A.net.cs2;
+      nfb += ok ? 0u : 1u;
+      if (A.c_out) A.c_out[id] = c;
+      if (A.rec) {
+        const double mu = (double)pos * (double)c;
+        if (A.rec_float)
+          ((float*)A.rec)[id] = (float)mu;
+        else
+          ((double*)A.rec)[id] = mu;
+        if (A.mut_out) A.mut_out[id] = mu;
+      }
+    }
+  }
+  if (A.fallback) {
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) nfb += __shfl_xor(nfb, o);
+    if (lane == 0 && nfb) atomicAdd(A.fallback, nfb);
+  }
+}
+
+int infer_grid(long long n) {
+  long long b = (n + 63) / 64;
+  return (int)std::max(1LL, std::min(b, 2048LL));
+}
+
+// ---------------------------------------------------------------------------------------
+// Training: loss and gradient of sum w (c - y)^2 * inv_wsum over the samples idx[0..n-1].
+// Each wave handles 32 samples per pass (two forward tiles of 16) and accumulates its
+// weight gradients in MFMA accumulators; per-wave partials go to `work`, then one pass sums
+// them in a fixed order.
+// ---------------------------------------------------------------------------------------
+struct GradArgs {
+  MlpNet net;
+  const float* feat;    // [6][nfeat]
+  long long nfeat;
+  const float* target;  // [nfeat]
+  const float* weight;  // [nfeat]
+  const int* idx;       // [n] sample node numbers
+  long long n;
+  float inv_wsum;
+  float* work;          // [blocks * 4][kMlpP + 1]
+};
+
+constexpr int kGradBlocksMax = 512;
+
+__global__ void __launch_bounds__(256) k_mlp_grad(GradArgs A) {
+  __shared__ __attribute__((aligned(16))) __bf16 W2s[64 * HS];  // W2[j][k] at [j][k]
+  __shared__ __attribute__((aligned(16))) __bf16 W2t[64 * HS];  // W2[j][k] at [k][j]
+  // Per-wave scratch: h1 and dL/da2 sample-major (B operands of layer 2 and of
+  // dh1 = W2^T da2), h1, dL/da2 and dL/da1 unit-major over the wave's 32 samples (operands
+  // of dW2 = da2^T h1 and dW1 = da1^T x), and the inputs input-major (rows 6..15 zero).
+  __shared__ __attribute__((aligned(16))) __bf16 sH1[4][2][16 * HS];
+  __shared__ __attribute__((aligned(16))) __bf16 sDA2[4][2][16 * HS];
+  __shared__ __attribute__((aligned(16))) __bf16 sH1T[4][64 * TS];
+  __shared__ __attribute__((aligned(16))) __bf16 sDA2T[4][64 * TS];
+  __shared__ __attribute__((aligned(16))) __bf16 sDA1T[4][64 * TS];
+  __shared__ __attribute__((aligned(16))) __bf16 sXT[4][16 * TS];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, g = lane >> 4, s = lane & 15;
+  const float* __restrict__ th = A.net.theta;
+  __bf16* const H1T = sH1T[wv];
+  __bf16* const DA2T = sDA2T[wv];
+  __bf16* const DA1T = sDA1T[wv];
+  __bf16* const XT = sXT[wv];
+  for (int e = threadIdx.x; e < kMlpH * kMlpH; e += 256) {
+    const int j = e / kMlpH, k = e % kMlpH;
+    const __bf16 v = (__bf16)th[kOffW2 + e];
+    W2s[j * HS + k] = v;
+    W2t[k * HS + j] = v;
+  }
+  for (int e = lane; e < 16 * TS; e += 64) XT[e] = (__bf16)0.f;
+  __syncthreads();
+  bf16x8 w1[4];
+#pragma unroll
+  for (int t = 0; t < 4; ++t) w1[t] = w1_frag(th, t, lane);
+  const f32x4 zero = {0.f, 0.f, 0.f, 0.f};
+  f32x4 dW2[4][4], dW1[4];
+#pragma unroll
+  for (int a = 0; a < 4; ++a) {
+    dW1[a] = zero;
+#pragma unroll
+    for (int b = 0; b < 4; ++b) dW2[a][b] = zero;
+  }
+  float db1[4][4], db2[4][4], dw3[4][4];
+#pragma unroll
+  for (int t = 0; t < 4; ++t)
+#pragma unroll
+    for (int i = 0; i < 4; ++i) db1[t][i] = db2[t][i] = dw3[t][i] = 0.f;
+  float db3 = 0.f, loss = 0.f;
+
+  for (long long base = (long long)blockIdx.x * 128; base < A.n;
+       base += (long long)gridDim.x * 128) {
+    const long long chunk = base + wv * 32;
+    for (int sub = 0; sub < 2; ++sub) {
+      const int sl = sub * 16 + s;
+      const long long si = chunk + sl;
+      float x[kMlpIn] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+      float y = 0.f, w = 0.f;
+      if (g == 0 && si < A.n) {
+        const long long gi = A.idx[si];
+#pragma unroll
+        for (int c = 0; c < kMlpIn; ++c)
+          x[c] = (A.feat[c * A.nfeat + gi] - A.net.norm.mean[c]) * A.net.norm.inv_std[c];
+        y = A.target[gi];
+        w = A.weight[gi];
+      }
+      if (g == 0)
+#pragma unroll
+        for (int c = 0; c < kMlpIn; ++c) XT[c * TS + sl] = (__bf16)x[c];
+      f32x4 a1[4], a2[4];
+      const float z = forward16(th, w1, W2s, x, lane, sH1[wv][sub], a1, a2);
+      const float wb = __shfl(w, s), yb = __shfl(y, s);
+      const float r = softplus_f(z) - yb;
+      const float dz = 2.f * wb * r * sigmoid_f(z) * A.inv_wsum;
+      if (g == 0) {
+        loss += wb * r * r * A.inv_wsum;
+        db3 += dz;
+      }
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        bf16x4 d4;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          const int j = 16 * t + 4 * g + i;
+          H1T[j * TS + sl] = (__bf16)gelu_f(a1[t][i]);
+          dw3[t][i] += dz * gelu_f(a2[t][i]);
+          const float da2 = dz * th[kOffW3 + j] * gelu_grad_f(a2[t][i]);
+          db2[t][i] += da2;
+          d4[i] = (__bf16)da2;
+          DA2T[j * TS + sl] = d4[i];
+        }
+        *(bf16x4*)&sDA2[wv][sub][s * HS + 16 * t + 4 * g] = d4;
+      }
+      __syncthreads();
+      // dh1^T = W2^T da2^T, then da1 = dh1 gelu'(a1).
+#pragma unroll
+      for (int tk = 0; tk < 4; ++tk) {
+        f32x4 acc = zero;
+#pragma unroll
+        for (int kb = 0; kb < 2; ++kb)
+          acc = mfma16(*(const bf16x8*)&W2t[(16 * tk + s) * HS + 32 * kb + 8 * g],
+                       *(const bf16x8*)&sDA2[wv][sub][s * HS + 32 * kb + 8 * g], acc);
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          const float da1 = acc[i] * gelu_grad_f(a1[tk][i]);
+          db1[tk][i] += da1;
+          DA1T[(16 * tk + 4 * g + i) * TS + sl] = (__bf16)da1;
+        }
+      }
+    }
+    __syncthreads();
+    // Weight gradients over the wave's 32 samples: dW2 = da2^T h1, dW1 = da1^T x.
+#pragma unroll
+    for (int tj = 0; tj < 4; ++tj) {
+      const bf16x8 a = *(const bf16x8*)&DA2T[(16 * tj + s) * TS + 8 * g];
+#pragma unroll
+      for (int tk = 0; tk < 4; ++tk)
+        dW2[tj][tk] = mfma16(a, *(const bf16x8*)&H1T[(16 * tk + s) * TS + 8 * g], dW2[tj][tk]);
+      dW1[tj] = mfma16(*(const bf16x8*)&DA1T[(16 * tj + s) * TS + 8 * g],
+                       *(const bf16x8*)&XT[s * TS + 8 * g], dW1[tj]);
+    }
+    __syncthreads();
+  }
+
+  float* P = A.work + (size_t)(blockIdx.x * 4 + wv) * (kMlpP + 1);
+#pragma unroll
+  for (int tj = 0; tj < 4; ++tj)
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int j = 16 * tj + 4 * g + i;
+#pragma unroll
+      for (int tk = 0; tk < 4; ++tk) P[kOffW2 + j * kMlpH + 16 * tk + s] = dW2[tj][tk][i];
+      if (s < kMlpIn) P[kOffW1 + j * kMlpIn + s] = dW1[tj][i];
+    }
+#pragma unroll
+  for (int t = 0; t < 4; ++t)
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      float a = db1[t][i], b = db2[t][i], c = dw3[t][i];
+#pragma unroll
+      for (int o = 1; o < 16; o <<= 1) {
+        a += __shfl_xor(a, o);
+        b += __shfl_xor(b, o);
+        c += __shfl_xor(c, o);
+      }
+      if (s == 0) {
+        const int j = 16 * t + 4 * g + i;
+        P[kOffB1 + j] = a;
+        P[kOffB2 + j] = b;
+        P[kOffW3 + j] = c;
+      }
+    }
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    db3 += __shfl_xor(db3, o);
+    loss += __shfl_xor(loss, o);
+  }
+  if (lane == 0) {
+    P[kOffB3] = db3;
+    P[kMlpP] = loss;
+  }
+}
+
+// grad[p] = sum over the per-wave partials, in wave order; loss likewise.
+__global__ void k_mlp_reduce(const float* __restrict__ work, int nparts, float* __restrict__ grad,
+                             float* __restrict__ loss) {
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p > kMlpP) return;
+  float acc = 0.f;
+  for (int w = 0; w < nparts; ++w) acc += work[(size_t)w * (kMlpP + 1) + p];
+  if (p < kMlpP)
+    grad[p] = acc;
+  else if (loss)
+    loss[0] = acc;
+}
+
+// Adam (Kingma & Ba), step counted from 1.
+__global__ void k_mlp_adam(float* __restrict__ theta, const float* __restrict__ grad,
+                           float* __restrict__ m, float* __restrict__ v, float lr, float b1,
+                           float b2, float eps, float c1, float c2) {
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= kMlpP) return;
+  const float gp = grad[p];
+  const float mp = b1 * m[p] + (1.f - b1) * gp;
+  const float vp = b2 * v[p] + (1.f - b2) * gp * gp;
+  m[p] = mp;
+  v[p] = vp;
+  theta[p] -= lr * (mp / c1) / (sqrtf(vp / c2) + eps);
+}
+
+// Input statistics over the samples with weight > 0 (one block, fixed order): mean,
+// standard deviation, minimum and maximum of each input, in double.
+__global__ void __launch_bounds__(256) k_mlp_stats(const float* __restrict__ feat,
+                                                   const float* __restrict__ weight, long long n,
+                                                   double* __restrict__ out) {
+  __shared__ double red[5][256];
+  for (int c = 0; c < kMlpIn; ++c) {
+    double s1 = 0.0, s2 = 0.0, cnt = 0.0, lo = INFINITY, hi = -INFINITY;
+    for (long long i = threadIdx.x; i < n; i += 256) {
+      if (!(weight[i] > 0.f)) continue;
+      const double v = feat[c * n + i];
+      if (!isfinite(v)) continue;
+      s1 += v;
+      s2 += v * v;
+      cnt += 1.0;
+      lo = fmin(lo, v);
+      hi = fmax(hi, v);
+    }
+    red[0][threadIdx.x] = s1;
+    red[1][threadIdx.x] = s2;
+    red[2][threadIdx.x] = cnt;
+    red[3][threadIdx.x] = lo;
+    red[4][threadIdx.x] = hi;
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+      if ((int)threadIdx.x < o) {
+        red[0][threadIdx.x] += red[0][threadIdx.x + o];
+        red[1][threadIdx.x] += red[1][threadIdx.x + o];
+        red[2][threadIdx.x] += red[2][threadIdx.x + o];
+        red[3][threadIdx.x] = fmin(red[3][threadIdx.x], red[3][threadIdx.x + o]);
+        red[4][threadIdx.x] = fmax(red[4][threadIdx.x], red[4][threadIdx.x + o]);
+      }
+      __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+      const double k = red[2][0] > 0 ? red[2][0] : 1.0;
+      const double mean = red[0][0] / k;
+      out[5 * c + 0] = mean;
+      out[5 * c + 1] = sqrt(fmax(red[1][0] / k - mean * mean, 0.0));
+      out[5 * c + 2] = red[3][0];
+      out[5 * c + 3] = red[4][0];
+      out[5 * c + 4] = red[2][0];
+    }
+    __syncthreads();
+  }
+}
+
+// ---------------------------------------------------------------------------------------
+// Training data: 2 x 2 x 2 box filter of a fine state onto the coarse grid, and the
+// least-squares coefficient target on the coarse grid.
+// ---------------------------------------------------------------------------------------
+__global__ void k_box_filter(Dims Df, const double* __restrict__ qf, Dims Dc,
+                             double* __restrict__ qc, double* __restrict__ sig) {
+  const long long id = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (id >= Dc.N) return;
+  const int i = (int)(id % Dc.n[0]);
+  const int j = (int)((id / Dc.n[0]) % Dc.n[1]);
+  const int k = (int)(id / ((long long)Dc.n[0] * Dc.n[1]));
+  double m[5] = {0, 0, 0, 0, 0}, uu[6] = {0, 0, 0, 0, 0, 0};
+  for (int c3 = 0; c3 < 2; ++c3)
+    for (int c2 = 0; c2 < 2; ++c2)
+      for (int c1 = 0; c1 < 2; ++c1) {
+        const long long f = nid(Df, 2 * i + c1, 2 * j + c2, 2 * k + c3);
+        double q[5];
+        for (int c = 0; c < 5; ++c) q[c] = qf[c * Df.N + f];
+        for (int c = 0; c < 5; ++c) m[c] += q[c];
+        const double ir = 1.0 / q[0];
+        uu[0] += q[1] * q[1] * ir;
+        uu[1] += q[2] * q[2] * ir;
+        uu[2] += q[3] * q[3] * ir;
+        uu[3] += q[1] * q[2] * ir;
+        uu[4] += q[1] * q[3] * ir;
+        uu[5] += q[2] * q[3] * ir;
+      }
+  for (int c = 0; c < 5; ++c) {
+    m[c] *= 0.125;
+    qc[c * Dc.N + id] = m[c];
+  }
+  const double ir = 1.0 / m[0];
+  const int a[6] = {1, 2, 3, 1, 1, 2}, b[6] = {1, 2, 3, 2, 3, 3};
+  for (int c = 0; c < 6; ++c) sig[c * Dc.N + id] = 0.125 * uu[c] - m[a[c]] * m[b[c]] * ir;
+}
+
+struct TargetArgs {
+  Dims D;
+  const double* q;     // filtered state on the coarse grid [5][N]
+  const double* sig;   // subgrid stress [6][N]: 00, 11, 22, 01, 02, 12
+  const double* S;     // coarse metrics
+  const double* jinv;
+  float smin;
+  float* feat;         // [6][N]
+  float* smag;         // [N]
+  float* target;       // [N]
+  float* weight;       // [N]
+};
+
+__device__ __forceinline__ void velocity_of(const double* q, long long N, long long o, double* u) {
+  const double ir = 1.0 / q[o];
+  u[0] = q[N + o] * ir;
+  u[1] = q[2 * N + o] * ir;
+  u[2] = q[3 * N + o] * ir;
+}
+
+__global__ void k_mlp_target(TargetArgs A) {
+  const Dims& D = A.D;
+  const long long o = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (o >= D.N) return;
+  const long long N = D.N;
+  const int ix[3] = {(int)(o % D.n[0]), (int)((o / D.n[0]) % D.n[1]),
+                     (int)(o / ((long long)D.n[0] * D.n[1]))};
+  double d[3][3];  // d[e][m] = delta_e u_m
+  double u0[3];
+  velocity_of(A.q, N, o, u0);
+  for (int e = 0; e < 3; ++e) {
+    const int n = D.n[e], m = ix[e];
+    const long long stride = e == 0 ? 1 : (e == 1 ? D.n[0] : (long long)D.n[0] * D.n[1]);
+    double ua[3], ub[3];
+    if (D.per[e] || (m > 0 && m < n - 1)) {
+      const int mp = m + 1 == n ? 0 : m + 1, mm = m == 0 ? n - 1 : m - 1;
+      velocity_of(A.q, N, o + (mp - m) * stride, ua);
+      velocity_of(A.q, N, o + (mm - m) * stride, ub);
+      for (int c = 0; c < 3; ++c) d[e][c] = 0.5 * (ua[c] - ub[c]);
+    } else {
+      const int sg = m == 0 ? 1 : -1;
+      velocity_of(A.q, N, o + sg * stride, ua);
+      velocity_of(A.q, N, o + 2 * sg * stride, ub);
+      for (int c = 0; c < 3; ++c) d[e][c] = 0.5 * sg * (-3.0 * u0[c] + 4.0 * ua[c] - ub[c]);
+    }
+  }
+  double s9[9];
+  for (int c = 0; c < 9; ++c) s9[c] = A.S[c * N + o];
+  const double jv = A.jinv[o];
+  double g[3][3];
+  velocity_gradient<double>(s9, d, jv, g);
+  double f[6];
+  const double sm = mlp_invariants<double>(g, f);
+  for (int c = 0; c < 6; ++c) A.feat[c * N + o] = (float)f[c];
+  A.smag[o] = (float)sm;
+  // c* = max(0, -sig^d : S^d / (2 rho Delta^2 |S| S^d : S^d)).
+  double S[3][3];
+  for (int m = 0; m < 3; ++m)
+    for (int n = 0; n < 3; ++n) S[m][n] = 0.5 * (g[m][n] + g[n][m]);
+  const double trS = S[0][0] + S[1][1] + S[2][2];
+  const double sg[3][3] = {{A.sig[o], A.sig[3 * N + o], A.sig[4 * N + o]},
+                           {A.sig[3 * N + o], A.sig[N + o], A.sig[5 * N + o]},
+                           {A.sig[4 * N + o], A.sig[5 * N + o], A.sig[2 * N + o]}};
+  const double trs = sg[0][0] + sg[1][1] + sg[2][2];
+  double num = 0.0, ss = 0.0;
+  for (int m = 0; m < 3; ++m)
+    for (int n = 0; n < 3; ++n) {
+      const double sd = S[m][n] - (m == n ? trS / 3.0 : 0.0);
+      const double gd = sg[m][n] - (m == n ? trs / 3.0 : 0.0);
+      num -= gd * sd;
+      ss += sd * sd;
+    }
+  const double dl = jv > 0.0 ? cbrt(jv) : 0.0;
+  const double den = 2.0 * A.q[o] * dl * dl * sm * ss;
+  double c = (den > 0.0 && jv > 0.0) ? num / den : 0.0;
+  c = c > 0.0 ? c : 0.0;
+  A.target[o] = (float)c;
+  A.weight[o] = (is_updated(D, ix[0], ix[1], ix[2]) && sm >= (double)A.smin && jv > 0.0) ? 1.f : 0.f;
+}
+
+}  // namespace
+
+hipError_t lesmi::launch_mlp_closure(const MlpClosureArgs& C, hipStream_t s) {
+  InferArgs A{};
+  A.net = C.net;
+  A.feat = C.feat;
+  A.pos = C.scale;
+  A.n = C.n;
+  A.rec = C.mut_rec;
+  A.rec_float = C.mixed;
+  A.mut_out = C.mut_out;
+  A.fallback = C.fallback;
+  hipLaunchKernelGGL(k_mlp_infer, dim3(infer_grid(C.n)), dim3(256), 0, s, A);
+  return hipGetLastError();
+}
+
+extern "C" {
+
+long long les_mlp_work_size(long long n) {
+  const long long blocks = std::max(1LL, std::min((n + 127) / 128, (long long)kGradBlocksMax));
+  return blocks * 4 * (kMlpP + 1);
+}
+
+int les_mlp_coefficient(const float* theta, const les_mlp_norm* norm, float cs2,
+                        const float* feat, const float* smag, long long n, float* c,
+                        unsigned* fallback, void* stream) {
+  if (!theta || !norm || !feat || !smag || !c || n < 0) return LES_EINVAL;
+  if (n == 0) return LES_OK;
+  InferArgs A{};
+  A.net.theta = theta;
+  A.net.norm = *norm;
+  A.net.cs2 = cs2;
+  A.feat = feat;
+  A.pos = smag;
+  A.n = n;
+  A.c_out = c;
+  A.fallback = fallback;
+  hipLaunchKernelGGL(k_mlp_infer, dim3(infer_grid(n)), dim3(256), 0, (hipStream_t)stream, A);
+  return hipGetLastError() == hipSuccess ? LES_OK : LES_EHIP;
+}
+
+int les_mlp_loss_grad(const float* theta, const les_mlp_norm* norm, const float* feat,
+                      long long nfeat, const float* target, const float* weight, const int* idx,
+                      long long n, float inv_wsum, float* grad, float* loss, float* work,
+                      void* stream) {
+  if (!theta || !norm || !feat || !target || !weight || !idx || !grad || !work || n < 1 ||
+      nfeat < 1)
+    return LES_EINVAL;
+  hipStream_t s = (hipStream_t)stream;
+  GradArgs A{};
+  A.net.theta = theta;
+  A.net.norm = *norm;
+  A.feat = feat;
+  A.nfeat = nfeat;
+  A.target = target;
+  A.weight = weight;
+  A.idx = idx;
+  A.n = n;
+  A.inv_wsum = inv_wsum;
+  A.work = work;
+  const int blocks = (int)(les_mlp_work_size(n) / (4 * (kMlpP + 1)));
+  hipLaunchKernelGGL(k_mlp_grad, dim3(blocks), dim3(256), 0, s, A);
+  hipLaunchKernelGGL(k_mlp_reduce, dim3((kMlpP + 1 + 255) / 256), dim3(256), 0, s, work,
+                     blocks * 4, grad, loss);
+  return hipGetLastError() == hipSuccess ? LES_OK : LES_EHIP;
+}
+
+int les_mlp_adam(float* theta, const float* grad, float* m, float* v, int step, float lr,
+                 float beta1, float beta2, float eps, void* stream) {
+  if (!theta || !grad || !m || !v || step < 1) return LES_EINVAL;
+  const float c1 = 1.f - powf(beta1, (float)step), c2 = 1.f - powf(beta2, (float)step);
+  hipLaunchKernelGGL(k_mlp_adam, dim3((kMlpP + 255) / 256), dim3(256), 0, (hipStream_t)stream,
+                     theta, grad, m, v, lr, beta1, beta2, eps, c1, c2);
+  return hipGetLastError() == hipSuccess ? LES_OK : LES_EHIP;
+}
+
+int les_mlp_fit_norm(const float* feat, const float* weight, long long n, float widen,
+                     les_mlp_norm* out, void* stream) {
+  if (!feat || !weight || !out || n < 1 || widen < 0.f) return LES_EINVAL;
+  hipStream_t s = (hipStream_t)stream;
+  double* d = nullptr;
+  if (hipMalloc((void**)&d, 30 * sizeof(double)) != hipSuccess) return LES_ENOMEM;
+  hipLaunchKernelGGL(k_mlp_stats, dim3(1), dim3(256), 0, s, feat, weight, n, d);
+  double h[30];
+  hipError_t e = hipMemcpyAsync(h, d, sizeof h, hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  (void)hipFree(d);
+  if (e != hipSuccess) return LES_EHIP;
+  for (int c = 0; c < kMlpIn; ++c) {
+    if (!(h[5 * c + 4] > 0.0)) return LES_EINVAL;  // no sample with weight > 0
+    const double sd = h[5 * c + 1] > 0.0 ? h[5 * c + 1] : 1.0;
+    const double span = h[5 * c + 3] - h[5 * c + 2];
+    out->mean[c] = (float)h[5 * c];
+    out->inv_std[c] = (float)(1.0 / sd);
+    out->lo[c] = (float)(h[5 * c + 2] - widen * span);
+    out->hi[c] = (float)(h[5 * c + 3] + widen * span);
+  }
+  return LES_OK;
+}
+
+int les_filter_target(les_ctx* fine, les_ctx* coarse, const double* q_fine, float smin,
+                      double* q_coarse, double* sigma, float* feat, float* smag, float* target,
+                      float* weight, void* stream) {
+  if (!fine || !coarse || !q_fine || !q_coarse || !sigma || !feat || !smag || !target ||
+      !weight)
+    return LES_EINVAL;
+  const Dims& Df = fine->dims;
+  const Dims& Dc = coarse->dims;
+  for (int d = 0; d < 3; ++d)
+    if (Df.n[d] != 2 * Dc.n[d]) {
+      coarse->err = "les_filter_target: the fine grid must have twice the coarse nodes";
+      return LES_EINVAL;
+    }
+  hipStream_t s = (hipStream_t)stream;
+  const unsigned blocks = (unsigned)((Dc.N + 255) / 256);
+  hipLaunchKernelGGL(k_box_filter, dim3(blocks), dim3(256), 0, s, Df, q_fine, Dc, q_coarse,
+                     sigma);
+  TargetArgs A{};
+  A.D = Dc;
+  A.q = q_coarse;
+  A.sig = sigma;
+  A.S = coarse->S;
+  A.jinv = coarse->jinv;
+  A.smin = smin;
+  A.feat = feat;
+  A.smag = smag;
+  A.target = target;
+  A.weight = weight;
+  hipLaunchKernelGGL(k_mlp_target, dim3(blocks), dim3(256), 0, s, A);
+  return hipGetLastError() == hipSuccess ? LES_OK : LES_EHIP;
+}
+
+}  // extern "C"

@@ -36,6 +36,11 @@ struct StageArgs {
   double alpha;
   int tile;   // k_stage_planes tile shape, index into kTileNames
   int kmin;   // smallest z-chunk depth (0 = default)
+  // Learned closure (k_nodes): inputs [6][N], scale rho Delta^2 |S| [N] and |S| [N] of the
+  // network; each may be null.
+  float* feat;
+  float* fscale;
+  float* fsmag;
 };
 
 constexpr int kNumTiles = 6;

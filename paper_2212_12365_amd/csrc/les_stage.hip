@@ -14,6 +14,7 @@
 #include <algorithm>
 
 #include "les_common.h"
+#include "les_mlp.h"
 #include "les_stage.h"
 
 namespace lesmi {
@@ -137,6 +138,17 @@ __device__ __forceinline__ void nodes_block(const StageArgs& A, int bx, int by, 
   r[(kRecNu + 1) * N + o] = nu[1];
   r[(kRecNu + 2) * N + o] = nu[2];
   if (A.mut_out) A.mut_out[o] = (double)mut;
+  if (A.feat || A.fscale || A.fsmag) {  // inputs of the learned closure
+    R g[3][3], f[kMlpIn];
+    velocity_gradient<R>(sm, du, jinv, g);
+    const R smag = mlp_invariants<R>(g, f);
+    if (A.feat)
+#pragma unroll
+      for (int c = 0; c < kMlpIn; ++c) A.feat[c * N + o] = (float)f[c];
+    const R dl = jinv > (R)0 ? cbrt(jinv) : (R)0;
+    if (A.fscale) A.fscale[o] = (float)((R)s.rho * dl * dl * smag);
+    if (A.fsmag) A.fsmag[o] = (float)smag;
+  }
 }
 
 template <typename R>

@@ -12,6 +12,7 @@
 
 #include "les_bcdt.h"
 #include "les_common.h"
+#include "les_mlp.h"
 #include "les_stage.h"
 
 using namespace lesmi;
@@ -315,7 +316,7 @@ int validate(const les_params* p, Dims* D) {
       !(p->prandtl_sgs > 0.0))
     return LES_EINVAL;
   if (p->precision != LES_FP64 && p->precision != LES_MIXED) return LES_EINVAL;
-  if (p->closure != LES_SMAGORINSKY) return LES_EINVAL;
+  if (p->closure != LES_SMAGORINSKY && p->closure != LES_MLP) return LES_EINVAL;
   D->jet = jet ? 1 : 0;
   D->N = (long long)n[0] * n[1] * n[2];
   return LES_OK;
@@ -360,7 +361,8 @@ void free_ctx(les_ctx* c) {
   c->ev.clear();
   void* ptrs[] = {c->S, c->jinv, c->jac, c->bc.nff, c->bc.nin, c->bc.nex, c->bc.jetmask,
                   c->bc.axis, c->qa, c->qb, c->rec, c->S32, c->rec32, c->d_dt, c->d_dtpart,
-                  c->d_flag, c->d_partial, c->d_diag};
+                  c->d_flag, c->d_partial, c->d_diag, c->mlp_theta, c->mlp_feat,
+                  c->mlp_scale, c->mlp_fallback};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
 }
@@ -379,7 +381,37 @@ StageArgs stage_args(les_ctx* c, const double* q) {
   A.rec32 = c->rec32;
   A.tile = c->tile;
   A.kmin = c->kmin;
+  if (c->params.closure == LES_MLP) {
+    A.feat = c->mlp_feat;
+    A.fscale = c->mlp_scale;
+  }
   return A;
+}
+
+// Learned closure: replaces the node kernel's eddy-viscosity records by rho c Delta^2 |S|
+// with c from the network (or C_s^2 where it falls back); mut_out may receive a copy.
+hipError_t run_mlp_closure(les_ctx* c, double* mut_out, hipStream_t s) {
+  MlpClosureArgs M{};
+  M.net.theta = c->mlp_theta;
+  M.net.norm = c->mlp_norm;
+  M.net.cs2 = (float)(c->params.cs * c->params.cs);
+  M.feat = c->mlp_feat;
+  M.scale = c->mlp_scale;
+  M.n = c->dims.N;
+  M.mixed = c->params.precision == LES_MIXED;
+  M.mut_rec = M.mixed ? (void*)(c->rec32 + (size_t)kRecMut * c->dims.N)
+                      : (void*)(c->rec + (size_t)kRecMut * c->dims.N);
+  M.mut_out = mut_out;
+  M.fallback = c->mlp_fallback;
+  return launch_mlp_closure(M, s);
+}
+
+bool mlp_missing(les_ctx* c) {
+  if (c->params.closure == LES_MLP && !c->mlp_ready) {
+    c->err = "learned closure without a network (les_mlp_set_network)";
+    return true;
+  }
+  return false;
 }
 
 // Records the next event of the profiling ring (three per stage: before the node kernel,
@@ -409,6 +441,7 @@ int run_stage(les_ctx* c, const double* q, int mode, double* out, const double* 
   int rc = timed ? prof_mark(c, s) : LES_OK;
   if (rc) return rc;
   hipError_t e = launch_nodes(A, s);
+  if (e == hipSuccess && c->params.closure == LES_MLP) e = run_mlp_closure(c, nullptr, s);
   if (e == hipSuccess && timed) rc = prof_mark(c, s);
   if (rc) return rc;
   if (e == hipSuccess) e = launch_stage(A, s);
@@ -473,8 +506,13 @@ int les_init_grid(const les_params* params, const double* xyz, les_ctx** out) {
       dev_alloc(c, &c->d_diag, 8) || dev_alloc(c, &c->bc.nff, 3LL * ni * nk) ||
       dev_alloc(c, &c->bc.nin, 3LL * nj * nk) || dev_alloc(c, &c->bc.nex, 3LL * nj * nk) ||
       dev_alloc(c, &c->bc.jetmask, (long long)nj * nk) || dev_alloc(c, &c->bc.axis, 5LL * ni) ||
-      dev_alloc(c, &d_xyz, 3 * N))
+      dev_alloc(c, &d_xyz, 3 * N) ||
+      (params->closure == LES_MLP &&
+       (dev_alloc(c, &c->mlp_theta, kMlpP) || dev_alloc(c, &c->mlp_feat, 6 * N) ||
+        dev_alloc(c, &c->mlp_scale, N) || dev_alloc(c, &c->mlp_fallback, 1))))
     return bail(LES_ENOMEM);
+  if (c->mlp_fallback && hipMemset(c->mlp_fallback, 0, sizeof(unsigned)) != hipSuccess)
+    return bail(LES_EHIP);
   c->bc.rho_inf = params->rho_inf;
   for (int d = 0; d < 3; ++d) c->bc.u_inf[d] = params->u_inf[d];
   c->bc.p_inf = params->p_inf;
@@ -524,14 +562,18 @@ int les_init_grid(const les_params* params, const double* xyz, les_ctx** out) {
 
 int les_residual(les_ctx* c, const double* q, double* rhs, void* stream) {
   if (!c || !q || !rhs) return fail(c, LES_EINVAL, "null argument");
+  if (mlp_missing(c)) return LES_ESTATE;
   return run_stage(c, q, 0, rhs, nullptr, 0.0, (hipStream_t)stream);
 }
 
 int les_sgs_viscosity(les_ctx* c, const double* q, double* mu_t, void* stream) {
   if (!c || !q || !mu_t) return fail(c, LES_EINVAL, "null argument");
+  if (mlp_missing(c)) return LES_ESTATE;
   StageArgs A = stage_args(c, q);
   A.mut_out = mu_t;
   hipError_t e = launch_nodes(A, (hipStream_t)stream);
+  if (e == hipSuccess && c->params.closure == LES_MLP)
+    e = run_mlp_closure(c, mu_t, (hipStream_t)stream);
   if (e != hipSuccess) {
     c->err = std::string("k_nodes: ") + hipGetErrorString(e);
     return LES_EHIP;
@@ -548,6 +590,7 @@ int les_step(les_ctx* c, double* q, int nsteps, double cfl, double dt_fixed, dou
              void* stream) {
   if (!c || !q || nsteps < 0) return fail(c, LES_EINVAL, "bad argument");
   if (!(cfl > 0.0) && !(dt_fixed > 0.0)) return fail(c, LES_EINVAL, "need cfl > 0 or dt_fixed > 0");
+  if (mlp_missing(c)) return LES_ESTATE;
   hipStream_t s = (hipStream_t)stream;
   const Dims& D = c->dims;
   hipLaunchKernelGGL(k_set_int, dim3(1), dim3(1), 0, s, c->d_flag, 0);
@@ -649,6 +692,43 @@ int les_profile_read(les_ctx* c, double* nodes_ms, double* faces_ms, long long* 
   if (faces_ms) *faces_ms = tf;
   *stages = (long long)(c->nrec / 3);
   c->nrec = 0;
+  return LES_OK;
+}
+
+int les_mlp_set_network(les_ctx* c, const float* theta, const les_mlp_norm* norm) {
+  if (!c || !theta || !norm) return fail(c, LES_EINVAL, "null argument");
+  if (c->params.closure != LES_MLP) return fail(c, LES_ESTATE, "context has no learned closure");
+  for (int i = 0; i < kMlpIn; ++i)
+    if (!(norm->lo[i] <= norm->hi[i]) || !std::isfinite(norm->inv_std[i]) ||
+        !std::isfinite(norm->mean[i]))
+      return fail(c, LES_EINVAL, "bad input normalisation");
+  HIP_TRY(c, hipMemcpy(c->mlp_theta, theta, kMlpP * sizeof(float), hipMemcpyDeviceToDevice));
+  c->mlp_norm = *norm;
+  c->mlp_ready = true;
+  return LES_OK;
+}
+
+int les_mlp_fallback_count(les_ctx* c, unsigned long long* count) {
+  if (!c || !count) return LES_EINVAL;
+  if (!c->mlp_fallback) return fail(c, LES_ESTATE, "context has no learned closure");
+  unsigned v = 0;
+  HIP_TRY(c, hipMemcpy(&v, c->mlp_fallback, sizeof v, hipMemcpyDeviceToHost));
+  HIP_TRY(c, hipMemset(c->mlp_fallback, 0, sizeof v));
+  *count = v;
+  return LES_OK;
+}
+
+int les_mlp_features(les_ctx* c, const double* q, float* feat, float* smag, void* stream) {
+  if (!c || !q || !feat || !smag) return fail(c, LES_EINVAL, "null argument");
+  StageArgs A = stage_args(c, q);
+  A.feat = feat;
+  A.fsmag = smag;
+  A.fscale = nullptr;
+  hipError_t e = launch_nodes(A, (hipStream_t)stream);
+  if (e != hipSuccess) {
+    c->err = std::string("k_nodes: ") + hipGetErrorString(e);
+    return LES_EHIP;
+  }
   return LES_OK;
 }
 

@@ -46,6 +46,25 @@ class les_params(ctypes.Structure):
     ]
 
 
+class les_mlp_norm(ctypes.Structure):
+    _fields_ = [("mean", ctypes.c_float * 6), ("inv_std", ctypes.c_float * 6),
+                ("lo", ctypes.c_float * 6), ("hi", ctypes.c_float * 6)]
+
+    @classmethod
+    def from_arrays(cls, mean, inv_std, lo, hi):
+        n = cls()
+        for i in range(6):
+            n.mean[i], n.inv_std[i] = float(mean[i]), float(inv_std[i])
+            n.lo[i], n.hi[i] = float(lo[i]), float(hi[i])
+        return n
+
+    def arrays(self):
+        return tuple(np.array(list(a), dtype=np.float64)
+                     for a in (self.mean, self.inv_std, self.lo, self.hi))
+
+
+MLP_NPARAMS = 4673
+
 _lib = None
 
 
@@ -86,6 +105,21 @@ def load():
         lib.les_batch_destroy.restype = None
         lib.les_batch_last_error.argtypes = [vp]
         lib.les_batch_last_error.restype = ctypes.c_char_p
+        fp = ctypes.c_void_p
+        np_ = ctypes.POINTER(les_mlp_norm)
+        lib.les_mlp_set_network.argtypes = [vp, fp, np_]
+        lib.les_mlp_fallback_count.argtypes = [vp, ctypes.POINTER(ctypes.c_ulonglong)]
+        lib.les_mlp_features.argtypes = [vp, vp, fp, fp, vp]
+        lib.les_mlp_coefficient.argtypes = [fp, np_, ctypes.c_float, fp, fp, ctypes.c_longlong,
+                                            fp, vp, vp]
+        lib.les_mlp_work_size.argtypes = [ctypes.c_longlong]
+        lib.les_mlp_work_size.restype = ctypes.c_longlong
+        lib.les_mlp_loss_grad.argtypes = [fp, np_, fp, ctypes.c_longlong, fp, fp, vp,
+                                          ctypes.c_longlong, ctypes.c_float, fp, fp, fp, vp]
+        lib.les_mlp_adam.argtypes = [fp, fp, fp, fp, ctypes.c_int, ctypes.c_float, ctypes.c_float,
+                                     ctypes.c_float, ctypes.c_float, vp]
+        lib.les_mlp_fit_norm.argtypes = [fp, fp, ctypes.c_longlong, ctypes.c_float, np_, vp]
+        lib.les_filter_target.argtypes = [vp, vp, vp, ctypes.c_float, vp, vp, fp, fp, fp, fp, vp]
         lib.les_destroy.argtypes = [vp]
         lib.les_destroy.restype = None
         lib.les_last_error.argtypes = [vp]
@@ -133,6 +167,20 @@ def _dev(t, n_expected, what):
         raise ValueError(f"{what}: expected a contiguous float64 GPU tensor of "
                          f"{n_expected} elements")
     return ctypes.c_void_p(t.data_ptr())
+
+
+def _f32(t, n_expected, what):
+    import torch
+    if not isinstance(t, torch.Tensor) or not t.is_cuda or t.dtype != torch.float32 \
+            or not t.is_contiguous() or t.numel() != n_expected:
+        raise ValueError(f"{what}: expected a contiguous float32 GPU tensor of "
+                         f"{n_expected} elements")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _lib_check(rc, what):
+    if rc != LES_OK:
+        raise LesError(rc, what)
 
 
 class Context:
@@ -239,6 +287,28 @@ class Context:
     def updated_nodes(self):
         return int(self.lib.les_updated_nodes(self.handle))
 
+    # Learned closure ------------------------------------------------------------------
+    def mlp_set_network(self, theta, norm):
+        self._check(self.lib.les_mlp_set_network(self.handle, _f32(theta, MLP_NPARAMS, "theta"),
+                                                 ctypes.byref(norm)), "les_mlp_set_network")
+
+    def mlp_fallback_count(self):
+        n = ctypes.c_ulonglong(0)
+        self._check(self.lib.les_mlp_fallback_count(self.handle, ctypes.byref(n)),
+                    "les_mlp_fallback_count")
+        return n.value
+
+    def mlp_features(self, q, stream=None):
+        """(inputs [6][N], |S| [N]) of a state, float32 GPU tensors."""
+        import torch
+        feat = torch.empty((6,) + self.shape, dtype=torch.float32, device="cuda")
+        smag = torch.empty(self.shape, dtype=torch.float32, device="cuda")
+        self._check(self.lib.les_mlp_features(self.handle, _dev(q, 5 * self.n, "q"),
+                                              _f32(feat, 6 * self.n, "feat"),
+                                              _f32(smag, self.n, "smag"), _stream(stream)),
+                    "les_mlp_features")
+        return feat, smag
+
     def close(self):
         if self.handle and self.handle.value:
             self.lib.les_destroy(self.handle)
@@ -318,3 +388,84 @@ class Batch:
             self.close()
         except Exception:
             pass
+
+
+# Learned-closure kernels that do not need a context --------------------------------------
+def mlp_coefficient(theta, norm, cs2, feat, smag, stream=None):
+    """c [n] (float32 GPU) and the number of fallback samples."""
+    import torch
+    lib = load()
+    n = smag.numel()
+    c = torch.empty(n, dtype=torch.float32, device="cuda")
+    fb = torch.zeros(1, dtype=torch.int32, device="cuda")
+    _lib_check(lib.les_mlp_coefficient(_f32(theta, MLP_NPARAMS, "theta"), ctypes.byref(norm),
+                                       float(cs2), _f32(feat, 6 * n, "feat"),
+                                       _f32(smag, n, "smag"), n, _f32(c, n, "c"),
+                                       ctypes.c_void_p(fb.data_ptr()), _stream(stream)),
+               "les_mlp_coefficient")
+    return c, int(fb.item())
+
+
+def mlp_work_size(n):
+    return int(load().les_mlp_work_size(int(n)))
+
+
+def mlp_loss_grad(theta, norm, feat, target, weight, idx, inv_wsum, work=None, stream=None):
+    """(grad [NPARAMS], loss [1]) float32 GPU tensors for the samples idx (int32 GPU)."""
+    import torch
+    lib = load()
+    nfeat = target.numel()
+    n = idx.numel()
+    if idx.dtype != torch.int32 or not idx.is_cuda or not idx.is_contiguous():
+        raise ValueError("idx: expected a contiguous int32 GPU tensor")
+    if work is None:
+        work = torch.empty(mlp_work_size(n), dtype=torch.float32, device="cuda")
+    grad = torch.empty(MLP_NPARAMS, dtype=torch.float32, device="cuda")
+    loss = torch.empty(1, dtype=torch.float32, device="cuda")
+    _lib_check(lib.les_mlp_loss_grad(_f32(theta, MLP_NPARAMS, "theta"), ctypes.byref(norm),
+                                     _f32(feat, 6 * nfeat, "feat"), nfeat,
+                                     _f32(target, nfeat, "target"), _f32(weight, nfeat, "weight"),
+                                     ctypes.c_void_p(idx.data_ptr()), n, float(inv_wsum),
+                                     _f32(grad, MLP_NPARAMS, "grad"), _f32(loss, 1, "loss"),
+                                     _f32(work, mlp_work_size(n), "work"), _stream(stream)),
+               "les_mlp_loss_grad")
+    return grad, loss
+
+
+def mlp_adam(theta, grad, m, v, step, lr, beta1=0.9, beta2=0.999, eps=1e-8, stream=None):
+    _lib_check(load().les_mlp_adam(_f32(theta, MLP_NPARAMS, "theta"),
+                                   _f32(grad, MLP_NPARAMS, "grad"), _f32(m, MLP_NPARAMS, "m"),
+                                   _f32(v, MLP_NPARAMS, "v"), int(step), float(lr), float(beta1),
+                                   float(beta2), float(eps), _stream(stream)), "les_mlp_adam")
+
+
+def mlp_fit_norm(feat, weight, widen=0.1, stream=None):
+    n = weight.numel()
+    out = les_mlp_norm()
+    _lib_check(load().les_mlp_fit_norm(_f32(feat, 6 * n, "feat"), _f32(weight, n, "weight"), n,
+                                       float(widen), ctypes.byref(out), _stream(stream)),
+               "les_mlp_fit_norm")
+    return out
+
+
+def filter_target(fine, coarse, q_fine, smin, stream=None):
+    """Box-filtered state, subgrid stress, inputs, |S~|, target and weight on the coarse
+    grid (dict of GPU tensors)."""
+    import torch
+    nc = coarse.n
+    sh = coarse.shape
+    out = {"q": torch.empty((5,) + sh, dtype=torch.float64, device="cuda"),
+           "sigma": torch.empty((6,) + sh, dtype=torch.float64, device="cuda"),
+           "feat": torch.empty((6,) + sh, dtype=torch.float32, device="cuda"),
+           "smag": torch.empty(sh, dtype=torch.float32, device="cuda"),
+           "target": torch.empty(sh, dtype=torch.float32, device="cuda"),
+           "weight": torch.empty(sh, dtype=torch.float32, device="cuda")}
+    rc = load().les_filter_target(fine.handle, coarse.handle, _dev(q_fine, 5 * fine.n, "q_fine"),
+                                  float(smin), _dev(out["q"], 5 * nc, "q_coarse"),
+                                  _dev(out["sigma"], 6 * nc, "sigma"),
+                                  _f32(out["feat"], 6 * nc, "feat"), _f32(out["smag"], nc, "smag"),
+                                  _f32(out["target"], nc, "target"),
+                                  _f32(out["weight"], nc, "weight"), _stream(stream))
+    if rc != LES_OK:
+        raise LesError(rc, "les_filter_target", load().les_last_error(coarse.handle).decode())
+    return out
