@@ -15,8 +15,9 @@
  *
  * Ownership. The caller owns every array passed in; the context owns the grid metrics,
  * the Runge-Kutta stage buffers, the boundary data and the time-step scalar. Device memory
- * is allocated or freed only by les_init_grid, les_destroy, les_mlp_fit_norm and the batch
- * calls les_batch_create, les_batch_set_tuning, les_batch_autotune and les_batch_destroy.
+ * is allocated or freed only by les_init_grid, les_destroy, les_stats_reset (first call),
+ * les_mlp_fit_norm and the batch calls les_batch_create, les_batch_set_tuning,
+ * les_batch_autotune and les_batch_destroy.
  *
  * Streams. `stream` is a hipStream_t (NULL = the null stream). Every call except
  * les_init_grid and les_destroy is asynchronous on that stream, and may be issued from
@@ -136,6 +137,20 @@ int les_apply_bc(les_ctx* ctx, double* q, void* stream);
  * kinetic energy sum J^-1 rho|u|^2/2 / sum J^-1; out[1..5] = sum J^-1 Q_c. q DEVICE [5][N];
  * out HOST [6]. Synchronises the stream. */
 int les_diagnostics(les_ctx* ctx, const double* q, double* out, void* stream);
+
+/* Residual norms of the mass equation over updated nodes: out[0] = (mean of RHS_rho^2)^(1/2),
+ * out[1] = max |RHS_rho| (out HOST [2]). Uses the context's stage buffer; synchronises. */
+int les_residual_norms(les_ctx* ctx, const double* q, double* out, void* stream);
+
+/* Running statistics of the primitive variables (rho, u, v, w, p) at every node, summed in
+ * FP64 on the device. les_stats_reset starts (and on first use allocates) the
+ * accumulators; les_stats_accumulate adds the state q (DEVICE [5][N]) as one sample;
+ * les_stats_read writes the mean and the r.m.s. fluctuation (DEVICE [5][N] each, either may
+ * be NULL) and the number of samples (HOST, may be NULL). The jet centreline profile is the
+ * mean at j = 0. */
+int les_stats_reset(les_ctx* ctx);
+int les_stats_accumulate(les_ctx* ctx, const double* q, void* stream);
+int les_stats_read(les_ctx* ctx, double* mean, double* rms, long long* samples, void* stream);
 
 /* Copies the context's metrics to DEVICE arrays S [9][N] (S_d^c at index 3d + c) and
  * jinv [N]; either may be NULL. */

@@ -72,6 +72,16 @@ def _load():
     return _lib
 
 
+def primitives(q, gamma):
+    """(rho, u, v, w, p) of a conserved state (paper, LES formulation: equation of state
+    with the System-I total energy), shaped (5, ...)."""
+    q = np.asarray(q, dtype=np.float64)
+    rho = q[0]
+    u, v, w = q[1] / rho, q[2] / rho, q[3] / rho
+    p = (gamma - 1.0) * (q[4] - 0.5 * rho * (u * u + v * v + w * w))
+    return np.stack([rho, u, v, w, p])
+
+
 class OracleError(RuntimeError):
     def __init__(self, code, what):
         super().__init__(f"oracle {what} failed with code {code}")

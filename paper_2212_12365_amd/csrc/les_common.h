@@ -86,6 +86,11 @@ struct les_ctx {
   float* mlp_scale = nullptr;  // [N]
   unsigned* mlp_fallback = nullptr;
 
+  // Running statistics: sums of (rho, u, v, w, p) and of their squares [5][N], samples.
+  double* stat_sum = nullptr;
+  double* stat_sq = nullptr;
+  long long stat_n = 0;
+
   // Optional timing of the stage kernel launches with HIP events on the caller's stream.
   bool prof = false;
   std::vector<hipEvent_t> ev;

@@ -219,7 +219,6 @@ __global__ void k_diag_partial(Dims D, const double* __restrict__ q,
   __shared__ double red[6][kBlock];
   long long N = D.N;
   long long lo = (long long)blockIdx.x * chunk, hi = lo + chunk < N ? lo + chunk : N;
-  double acc[6] = {0, 0, 0, 0, 0, 0};  // vol, ke, then... packed below
   double tot[5] = {0, 0, 0, 0, 0};
   double vol = 0.0, ke = 0.0;
   for (long long id = lo + threadIdx.x; id < hi; id += blockDim.x) {
@@ -234,7 +233,6 @@ __global__ void k_diag_partial(Dims D, const double* __restrict__ q,
     ke += w * 0.5 * m2 / r;
     for (int c = 0; c < 5; ++c) tot[c] += w * q[(long long)c * N + id];
   }
-  (void)acc;
   // Slot 0 = ke, slots 1..5 = totals; the volume goes to a separate partial row.
   red[0][threadIdx.x] = ke;
   for (int c = 0; c < 5; ++c) red[1 + c][threadIdx.x] = tot[c];
@@ -263,6 +261,72 @@ __global__ void k_diag_final(const double* __restrict__ part, int nparts,
     for (int c = 0; c < 7; ++c) s[c] += part[(long long)b * 7 + c];
   out[0] = s[0] / s[6];
   for (int c = 0; c < 5; ++c) out[1 + c] = s[1 + c];
+}
+
+// Running statistics of the primitive variables (rho, u, v, w, p) at every node: one
+// sample adds x and x^2 in FP64.
+__global__ void k_stats_acc(Dims D, Phys P, const double* __restrict__ q, double* __restrict__ sum,
+                            double* __restrict__ sq) {
+  const long long id = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (id >= D.N) return;
+  const long long N = D.N;
+  const Prim s = prim_from_q(q[id], q[N + id], q[2 * N + id], q[3 * N + id], q[4 * N + id], P);
+  const double x[5] = {s.rho, s.u, s.v, s.w, s.p};
+  for (int c = 0; c < 5; ++c) {
+    sum[c * N + id] += x[c];
+    sq[c * N + id] += x[c] * x[c];
+  }
+}
+
+__global__ void k_stats_read(long long n, const double* __restrict__ sum,
+                             const double* __restrict__ sq, double count,
+                             double* __restrict__ mean, double* __restrict__ rms) {
+  const long long id = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (id >= n) return;
+  const double m = sum[id] / count;
+  if (mean) mean[id] = m;
+  if (rms) rms[id] = sqrt(fmax(sq[id] / count - m * m, 0.0));
+}
+
+// Sum of squares and largest magnitude of the mass residual over updated nodes, per fixed
+// node range; then one fixed-order pass.
+__global__ void k_rhs_norm_partial(Dims D, const double* __restrict__ rhs,
+                                   double* __restrict__ part, long long chunk) {
+  __shared__ double red[2][kBlock];
+  const long long lo = (long long)blockIdx.x * chunk, hi = lo + chunk < D.N ? lo + chunk : D.N;
+  double s2 = 0.0, mx = 0.0;
+  for (long long id = lo + threadIdx.x; id < hi; id += blockDim.x) {
+    const int i = (int)(id % D.n[0]);
+    const int j = (int)((id / D.n[0]) % D.n[1]);
+    const int k = (int)(id / ((long long)D.n[0] * D.n[1]));
+    if (!is_updated(D, i, j, k)) continue;
+    const double r = rhs[id];
+    s2 += r * r;
+    mx = fmax(mx, fabs(r));
+  }
+  red[0][threadIdx.x] = s2;
+  red[1][threadIdx.x] = mx;
+  __syncthreads();
+  for (int o = kBlock / 2; o > 0; o >>= 1) {
+    if ((int)threadIdx.x < o) {
+      red[0][threadIdx.x] += red[0][threadIdx.x + o];
+      red[1][threadIdx.x] = fmax(red[1][threadIdx.x], red[1][threadIdx.x + o]);
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x < 2) part[(long long)blockIdx.x * 2 + threadIdx.x] = red[threadIdx.x][0];
+}
+
+__global__ void k_rhs_norm_final(const double* __restrict__ part, int nparts, double nupd,
+                                 double* __restrict__ out) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  double s2 = 0.0, mx = 0.0;
+  for (int b = 0; b < nparts; ++b) {
+    s2 += part[2 * b];
+    mx = fmax(mx, part[2 * b + 1]);
+  }
+  out[0] = sqrt(s2 / nupd);
+  out[1] = mx;
 }
 
 __global__ void k_copy(long long n, const double* __restrict__ src, double* __restrict__ dst) {
@@ -362,7 +426,7 @@ void free_ctx(les_ctx* c) {
   void* ptrs[] = {c->S, c->jinv, c->jac, c->bc.nff, c->bc.nin, c->bc.nex, c->bc.jetmask,
                   c->bc.axis, c->qa, c->qb, c->rec, c->S32, c->rec32, c->d_dt, c->d_dtpart,
                   c->d_flag, c->d_partial, c->d_diag, c->mlp_theta, c->mlp_feat,
-                  c->mlp_scale, c->mlp_fallback};
+                  c->mlp_scale, c->mlp_fallback, c->stat_sum, c->stat_sq};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
 }
@@ -642,6 +706,59 @@ int les_diagnostics(les_ctx* c, const double* q, double* out, void* stream) {
   HIP_TRY(c, hipMemcpyAsync(out, c->d_diag, 6 * sizeof(double), hipMemcpyDeviceToHost, s));
   HIP_TRY(c, hipStreamSynchronize(s));
   return LES_OK;
+}
+
+int les_residual_norms(les_ctx* c, const double* q, double* out, void* stream) {
+  if (!c || !q || !out) return fail(c, LES_EINVAL, "null argument");
+  if (mlp_missing(c)) return LES_ESTATE;
+  hipStream_t s = (hipStream_t)stream;
+  int rc = run_stage(c, q, 0, c->qb, nullptr, 0.0, s);
+  if (rc) return rc;
+  const Dims& D = c->dims;
+  long long chunk = (D.N + kMaxPartials - 1) / kMaxPartials;
+  if (chunk < 1024) chunk = 1024;
+  const int nparts = (int)((D.N + chunk - 1) / chunk);
+  hipLaunchKernelGGL(k_rhs_norm_partial, dim3(nparts), dim3(kBlock), 0, s, D, c->qb,
+                     c->d_partial, chunk);
+  hipLaunchKernelGGL(k_rhs_norm_final, dim3(1), dim3(1), 0, s, c->d_partial, nparts,
+                     (double)c->n_updated, c->d_diag);
+  rc = launch_check(c, "residual norms");
+  if (rc) return rc;
+  HIP_TRY(c, hipMemcpyAsync(out, c->d_diag, 2 * sizeof(double), hipMemcpyDeviceToHost, s));
+  HIP_TRY(c, hipStreamSynchronize(s));
+  return LES_OK;
+}
+
+int les_stats_reset(les_ctx* c) {
+  if (!c) return LES_EINVAL;
+  const long long N = c->dims.N;
+  if (!c->stat_sum && (dev_alloc(c, &c->stat_sum, 5 * N) || dev_alloc(c, &c->stat_sq, 5 * N)))
+    return LES_ENOMEM;
+  HIP_TRY(c, hipMemset(c->stat_sum, 0, 5 * N * sizeof(double)));
+  HIP_TRY(c, hipMemset(c->stat_sq, 0, 5 * N * sizeof(double)));
+  c->stat_n = 0;
+  return LES_OK;
+}
+
+int les_stats_accumulate(les_ctx* c, const double* q, void* stream) {
+  if (!c || !q) return fail(c, LES_EINVAL, "null argument");
+  if (!c->stat_sum) return fail(c, LES_ESTATE, "statistics not started (les_stats_reset)");
+  hipLaunchKernelGGL(k_stats_acc, dim3(grid_for(c->dims.N)), dim3(kBlock), 0,
+                     (hipStream_t)stream, c->dims, c->phys, q, c->stat_sum, c->stat_sq);
+  int rc = launch_check(c, "statistics");
+  if (rc) return rc;
+  c->stat_n += 1;
+  return LES_OK;
+}
+
+int les_stats_read(les_ctx* c, double* mean, double* rms, long long* samples, void* stream) {
+  if (!c) return LES_EINVAL;
+  if (!c->stat_sum || c->stat_n == 0) return fail(c, LES_ESTATE, "no statistics sample");
+  const long long n = 5 * c->dims.N;
+  hipLaunchKernelGGL(k_stats_read, dim3(grid_for(n)), dim3(kBlock), 0, (hipStream_t)stream, n,
+                     c->stat_sum, c->stat_sq, (double)c->stat_n, mean, rms);
+  if (samples) *samples = c->stat_n;
+  return launch_check(c, "statistics");
 }
 
 int les_get_metrics(les_ctx* c, double* S, double* jinv, void* stream) {

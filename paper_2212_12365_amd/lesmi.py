@@ -120,6 +120,10 @@ def load():
                                      ctypes.c_float, ctypes.c_float, vp]
         lib.les_mlp_fit_norm.argtypes = [fp, fp, ctypes.c_longlong, ctypes.c_float, np_, vp]
         lib.les_filter_target.argtypes = [vp, vp, vp, ctypes.c_float, vp, vp, fp, fp, fp, fp, vp]
+        lib.les_residual_norms.argtypes = [vp, vp, dp, vp]
+        lib.les_stats_reset.argtypes = [vp]
+        lib.les_stats_accumulate.argtypes = [vp, vp, vp]
+        lib.les_stats_read.argtypes = [vp, vp, vp, ctypes.POINTER(ctypes.c_longlong), vp]
         lib.les_destroy.argtypes = [vp]
         lib.les_destroy.restype = None
         lib.les_last_error.argtypes = [vp]
@@ -248,6 +252,32 @@ class Context:
                                              out.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
                                              _stream(stream)), "les_diagnostics")
         return out
+
+    def residual_norms(self, q, stream=None):
+        """(r.m.s., max) of the mass residual over updated nodes."""
+        out = np.zeros(2)
+        self._check(self.lib.les_residual_norms(self.handle, _dev(q, 5 * self.n, "q"),
+                                                out.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                                _stream(stream)), "les_residual_norms")
+        return out
+
+    def stats_reset(self):
+        self._check(self.lib.les_stats_reset(self.handle), "les_stats_reset")
+
+    def stats_accumulate(self, q, stream=None):
+        self._check(self.lib.les_stats_accumulate(self.handle, _dev(q, 5 * self.n, "q"),
+                                                  _stream(stream)), "les_stats_accumulate")
+
+    def stats_read(self, stream=None):
+        """(mean [5][N], rms [5][N], samples) of (rho, u, v, w, p)."""
+        import torch
+        mean = torch.empty((5,) + self.shape, dtype=torch.float64, device="cuda")
+        rms = torch.empty_like(mean)
+        n = ctypes.c_longlong(0)
+        self._check(self.lib.les_stats_read(self.handle, _dev(mean, 5 * self.n, "mean"),
+                                            _dev(rms, 5 * self.n, "rms"), ctypes.byref(n),
+                                            _stream(stream)), "les_stats_read")
+        return mean, rms, n.value
 
     def metrics(self, stream=None):
         import torch

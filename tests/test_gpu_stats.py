@@ -1,0 +1,115 @@
+"""Diagnostics and statistics on the GPU against the oracle run step for step.
+
+* Running mean and r.m.s. of (rho, u, v, w, p) over a jet run: GPU accumulators against the
+  mean of the oracle's states; the centreline profile (mean at j = 0) within the 1 % bar in
+  both forms (FP64 agrees to round-off).
+* Kinetic-energy decay of the Taylor-Green vortex over 20 steps within 1 % in both forms.
+* Mass-residual norms against the oracle residual.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import synthetic as sy
+from gpu_cases import case
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch as t
+    assert t.cuda.is_available()
+    return t
+
+
+def _announce(what):
+    print(f"[gpu] {what}", flush=True)
+
+
+@pytest.fixture(scope="module")
+def jet_oracle_run():
+    p, xyz, q = case("jet_small")
+    o = oracle.Oracle(p, xyz)
+    q = o.apply_bc(q)
+    states = []
+    x = q.copy()
+    for _ in range(40):
+        x, _ = o.step(x, 1, cfl=0.5)
+        states.append(oracle.primitives(x, p.gamma))
+    a = np.stack(states)
+    return p, xyz, q, a.mean(0), np.sqrt(np.maximum((a * a).mean(0) - a.mean(0) ** 2, 0))
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_jet_statistics(torch, jet_oracle_run, precision):
+    _announce(f"jet statistics precision={precision}")
+    from paper_2212_12365_amd.lesmi import Context
+    p, xyz, q, mean_ref, rms_ref = jet_oracle_run
+    ctx = Context(p.replace(precision=precision), xyz)
+    g = torch.from_numpy(q).cuda()
+    ctx.stats_reset()
+    for _ in range(40):
+        ctx.step(g, 1, cfl=0.5)
+        ctx.stats_accumulate(g)
+    mean, rms, n = ctx.stats_read()
+    assert n == 40
+    mean = mean.cpu().numpy()
+    rms = rms.cpu().numpy()
+    cl = mean[1, :, 0, :].mean(0)       # centreline mean axial velocity, per station i
+    cl_ref = mean_ref[1, :, 0, :].mean(0)
+    err = np.max(np.abs(cl - cl_ref)) / np.max(np.abs(cl_ref))
+    print(f"centreline mean u: max rel err {err:.3e} (precision {precision})")
+    assert err <= (1e-10 if precision == 0 else 1e-2)
+    if precision == 0:
+        for c in range(5):
+            e = np.max(np.abs(mean[c] - mean_ref[c])) / np.max(np.abs(mean_ref[c]))
+            assert e <= 1e-10, (c, e)
+        # variances (the r.m.s. is the square root of a difference that vanishes where the
+        # field is steady, so compare before the root)
+        e = np.max(np.abs(rms ** 2 - rms_ref ** 2)) / np.max(mean_ref[1] ** 2)
+        assert e <= 1e-13, e
+    ctx.close()
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_tgv_kinetic_energy_decay(torch, precision):
+    _announce(f"tgv kinetic energy decay precision={precision}")
+    from paper_2212_12365_amd.lesmi import Context
+    p, xyz, q = case("tgv32")
+    o = oracle.Oracle(p, xyz)
+    ctx = Context(p.replace(precision=precision), xyz)
+    g = torch.from_numpy(q).cuda()
+    k0 = o.diagnostics(q)[0]
+    x = q.copy()
+    for step in range(1, 21):
+        x, _ = o.step(x, 1, cfl=0.5)
+        ctx.step(g, 1, cfl=0.5)
+        if step % 5 == 0:
+            dk_ref = k0 - o.diagnostics(x)[0]
+            dk = k0 - ctx.diagnostics(g)[0]
+            err = abs(dk - dk_ref) / abs(dk_ref)
+            print(f"step {step}: KE decay {dk:.6e} vs {dk_ref:.6e} rel err {err:.2e}")
+            # FP64: K agrees to ~1e-12 relative, and the decay is ~1e-3 of K
+            assert err <= (1e-6 if precision == 0 else 1e-2)
+    ctx.close()
+
+
+@pytest.mark.parametrize("name", ["jet_small", "skew24"])
+def test_residual_norms(torch, name):
+    _announce(f"residual norms {name}")
+    from paper_2212_12365_amd.lesmi import Context
+    p, xyz, q = case(name)
+    o = oracle.Oracle(p, xyz)
+    if p.bc[0] != 0:
+        q = o.apply_bc(q)
+    r = o.residual(q)[0]
+    upd = np.ones(p.shape, bool)
+    if p.bc[0] != 0:
+        upd[:, 0, :] = upd[:, -1, :] = False
+        upd[:, :, 0] = upd[:, :, -1] = False
+    ref = np.array([np.sqrt(np.mean(r[upd] ** 2)), np.max(np.abs(r[upd]))])
+    ctx = Context(p, xyz)
+    got = ctx.residual_norms(torch.from_numpy(q).cuda())
+    assert np.allclose(got, ref, rtol=1e-12), (got, ref)
+    ctx.close()
