@@ -7,8 +7,9 @@ curvilinear grid in FP64, with the state resident in HBM. The JSON line reports
 Mcell-RKstage/s (updated nodes x 5 stages x steps / wall time), the roofline position of the
 dominant kernel (the face kernel, timed live with HIP events on the stream it runs on), the
 same workload in the mixed-precision form, the 16-member batched ensemble against the same
-members run one after another, and the CPU oracle timed on a bounded sample of the same
-workload.
+members run one after another, the 384 x 192 x 192 jet in FP64, mixed precision (with its
+error against the FP64 run) and mixed precision with the learned closure, and the CPU oracle
+timed on a bounded sample of the same workload.
 """
 import argparse
 import hashlib
@@ -137,6 +138,61 @@ def run_batched(torch, steps, warmup):
             "speedup_vs_sequential": round(t_seq / t_b, 3)}
 
 
+def run_c3(torch, steps, warmup):
+    """The 384 x 192 x 192 jet: the mixed form stepped beside the FP64 form from the same
+    state (relative errors of rho, u and E after `steps` steps), and the mixed form with the
+    learned closure against the mixed form with Smagorinsky (throughput; the network holds
+    its seeded initial weights, which do not change the work)."""
+    import synthetic as sy
+    from paper_2212_12365_amd import closure
+    from paper_2212_12365_amd.lesmi import Context
+    n = (384, 192, 192)
+    params, xyz, q = sy.make_case("jet", n, seed=0)
+    out = {"grid": list(n)}
+
+    def timed(ctx, g):
+        ctx.step(g, warmup, cfl=0.5)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        ctx.step(g, steps, cfl=0.5)
+        torch.cuda.synchronize()
+        return time.perf_counter() - t0
+
+    c64 = Context(params, xyz)
+    g64 = torch.from_numpy(q).to("cuda")
+    c64.apply_bc(g64)
+    upd = c64.updated_nodes()
+    start = g64.clone()
+    t64 = timed(c64, g64)
+    c32 = Context(params.replace(precision=1), xyz)
+    g32 = start.clone()
+    t32 = timed(c32, g32)
+    # error of the mixed run against the FP64 run after the same warmup + steps
+    rho64, rho32 = g64[0], g32[0]
+    u64, u32 = g64[1] / g64[0], g32[1] / g32[0]
+
+    def rel(a, b):
+        return {"rel_l2": float(torch.linalg.vector_norm(a - b) / torch.linalg.vector_norm(b)),
+                "rel_linf": float((a - b).abs().max() / b.abs().max())}
+
+    out["fp64_value"] = round(upd * 5 * steps / t64 / 1e6, 3)
+    out["mixed_value"] = round(upd * 5 * steps / t32 / 1e6, 3)
+    out["mixed_speedup_vs_fp64"] = round(t64 / t32, 3)
+    out["mixed_vs_fp64_after_steps"] = {"steps": warmup + steps, "rho": rel(rho32, rho64),
+                                        "u": rel(u32, u64), "E": rel(g32[4], g64[4])}
+    del g64, c64
+    from paper_2212_12365_amd.lesmi import les_mlp_norm
+    cm = Context(params.replace(precision=1, closure=1), xyz)
+    nm = les_mlp_norm.from_arrays([0.0] * 6, [1.0] * 6, [-1e30] * 6, [1e30] * 6)
+    cm.mlp_set_network(closure.init_params(params.cs ** 2, seed=0), nm)
+    gm = start.clone()
+    tm = timed(cm, gm)
+    out["learned_closure_value"] = round(upd * 5 * steps / tm / 1e6, 3)
+    out["learned_closure_cost_vs_smagorinsky"] = round(tm / t32, 3)
+    out["steps"] = steps
+    return out
+
+
 def copy_calibration(gib=1.0, reps=5):
     """A plain device copy of known size, for scaling HBM counter readings."""
     import torch
@@ -206,6 +262,7 @@ def main():
             "speedup_vs_fp64": round(mx["rate"] / value, 3)}
     if args.forms:
         forms["batched"] = run_batched(torch, args.batch_steps, 2)
+        forms["jet384"] = run_c3(torch, args.batch_steps, 2)
     out = {
         "metric": "Mcell-RKstage updates/s and % HBM roofline, FP64 vs mixed vs batched",
         "value": round(value, 3),

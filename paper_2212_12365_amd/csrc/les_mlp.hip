@@ -35,13 +35,19 @@ __device__ __forceinline__ f32x4 mfma16(bf16x8 a, bf16x8 b, f32x4 c) {
   return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
 }
 
-__device__ __forceinline__ float gelu_f(float x) {
-  return 0.5f * x * (1.f + tanhf(kG0 * (x + kG1 * x * x * x)));
+// GELU in its tanh form, written through 0.5 (1 + tanh y) = 1 / (1 + exp(-2y)) with the
+// hardware exponential and reciprocal: gelu(x) = x s, s = 1 / (1 + exp(-2 k0 (x + k1 x^3))).
+__device__ __forceinline__ float gelu_sig(float x) {
+  const float y = kG0 * (x + kG1 * x * x * x);
+  return __frcp_rn(1.f + __expf(-2.f * y));
 }
 
+__device__ __forceinline__ float gelu_f(float x) { return x * gelu_sig(x); }
+
+// d gelu / dx = s + x s (1 - s) 2 k0 (1 + 3 k1 x^2).
 __device__ __forceinline__ float gelu_grad_f(float x) {
-  const float t = tanhf(kG0 * (x + kG1 * x * x * x));
-  return 0.5f * (1.f + t) + 0.5f * x * (1.f - t * t) * kG0 * (1.f + 3.f * kG1 * x * x);
+  const float s = gelu_sig(x);
+  return s + x * s * (1.f - s) * (2.f * kG0) * (1.f + 3.f * kG1 * x * x);
 }
 
 __device__ __forceinline__ float softplus_f(float z) {
@@ -226,6 +232,9 @@ struct InferArgs {
   unsigned* fallback; // optional count of fallback samples
 };
 
+// Each wave takes 64 samples per pass: lane l loads sample l (coalesced) and the next
+// pass's inputs are prefetched; the four 16-sample MFMA tiles of the pass get their inputs
+// by lane shuffles and hand z back to the loading lane.
 __global__ void __launch_bounds__(256) k_mlp_infer(InferArgs A) {
   __shared__ __attribute__((aligned(16))) __bf16 H[4][16 * HS];
   __shared__ __attribute__((aligned(16))) __bf16 Hl[4][16 * HS];
@@ -238,28 +247,37 @@ __global__ void __launch_bounds__(256) k_mlp_infer(InferArgs A) {
     w2_frag_split(th, t, 0, lane, w2h[t][0], w2l[t][0]);
     w2_frag_split(th, t, 1, lane, w2h[t][1], w2l[t][1]);
   }
-  unsigned nfb = 0;
-  for (long long base = (long long)blockIdx.x * 64; base < A.n;
-       base += (long long)gridDim.x * 64) {
-    const long long id = base + wv * 16 + s;
-    const bool mine = g == 0 && id < A.n;
-    float x[kMlpIn] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
-    float pos = 0.f;
-    bool ok = false;
-    if (mine) {
-      float f[kMlpIn];
+  const long long stride = (long long)gridDim.x * 256;
+  float f[kMlpIn], pos = 0.f;
+  auto load = [&](long long id) {
 #pragma unroll
-      for (int c = 0; c < kMlpIn; ++c) f[c] = A.feat[c * A.n + id];
-      pos = A.pos[id];
-      ok = mlp_input(A.net, f, pos, x);
+    for (int c = 0; c < kMlpIn; ++c) f[c] = id < A.n ? A.feat[c * A.n + id] : 0.f;
+    pos = id < A.n ? A.pos[id] : 0.f;
+  };
+  long long base = (long long)blockIdx.x * 256;
+  load(base + wv * 64 + lane);
+  unsigned nfb = 0;
+  for (; base < A.n; base += stride) {
+    const long long id = base + wv * 64 + lane;
+    float x[kMlpIn];
+    const float mypos = pos;
+    const bool ok = mlp_input(A.net, f, mypos, x);
+    load(id + stride);  // prefetch the next pass
+    float zmine = 0.f;
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      float xs[kMlpIn];
+#pragma unroll
+      for (int c = 0; c < kMlpIn; ++c) xs[c] = __shfl(x[c], s + 16 * t);
+      const float z = forward16_split(th, w1h, w1l, w2h, w2l, xs, lane, H[wv], Hl[wv]);
+      if (g == t) zmine = z;
     }
-    const float z = forward16_split(th, w1h, w1l, w2h, w2l, x, lane, H[wv], Hl[wv]);
-    if (mine) {
-      const float c = ok ? softplus_f(z) : A.net.cs2;
+    if (id < A.n) {
+      const float c = ok ? softplus_f(zmine) : A.net.cs2;
       nfb += ok ? 0u : 1u;
       if (A.c_out) A.c_out[id] = c;
       if (A.rec) {
-        const double mu = (double)pos * (double)c;
+        const double mu = (double)mypos * (double)c;
         if (A.rec_float)
           ((float*)A.rec)[id] = (float)mu;
         else
@@ -276,8 +294,8 @@ __global__ void __launch_bounds__(256) k_mlp_infer(InferArgs A) {
 }
 
 int infer_grid(long long n) {
-  long long b = (n + 63) / 64;
-  return (int)std::max(1LL, std::min(b, 2048LL));
+  long long b = (n + 255) / 256;
+  return (int)std::max(1LL, std::min(b, 1024LL));
 }
 
 // ---------------------------------------------------------------------------------------
