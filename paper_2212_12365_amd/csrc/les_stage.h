@@ -43,7 +43,7 @@ struct StageArgs {
   float* fsmag;
 };
 
-constexpr int kNumTiles = 6;
+constexpr int kNumTiles = 10;
 extern const char* const kTileNames[kNumTiles];
 
 hipError_t launch_nodes(const StageArgs& A, hipStream_t s);

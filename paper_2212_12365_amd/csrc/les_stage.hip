@@ -198,21 +198,22 @@ struct PlaneLds {
     struct {
       R W[6][NW];    // W0..W4 and p over the two-node ring
       R F[sNF][N1];  // other face inputs over the one-node ring
+      R DX[2][(TX + 2) * TY];  // scaled spectral radius and sensor along xi, xi-face nodes
+      R DY[2][TX * (TY + 2)];  // the same along eta, eta-face nodes
     } in;
     R H[5][NX + NY];
   };
 };
 
 // Face inputs of a node staged in LDS, read at the point of use. Tangential differences
-// are centred in-plane and staged along zeta; lb/nu along d come from the node records.
+// are centred in-plane and staged along zeta; lb/nu along d are given by the caller (staged
+// in LDS for xi and eta faces, prefetched into registers for zeta faces).
 template <int TX, int TY, int d, typename R>
 struct LdsNode {
   using PL = PlaneLds<TX, TY, R>;
   const PL& L;
   int p1, p2;
-  unsigned o;
-  const R* __restrict__ rec;
-  int N;
+  R lb_, nu_;
   __device__ R W(int c) const { return L.in.W[c][p2]; }
   __device__ R p() const { return L.in.W[5][p2]; }
   __device__ R f(int v) const { return L.in.F[sU + v][p1]; }  // u, v, w, T
@@ -220,8 +221,8 @@ struct LdsNode {
   __device__ R mut() const { return L.in.F[sMut][p1]; }
   __device__ R S(int c) const { return L.in.F[sS0 + c][p1]; }
   __device__ R jinv() const { return L.in.F[sJinv][p1]; }
-  __device__ R lb() const { return rec[(kRecLb + d) * N + o]; }
-  __device__ R nu() const { return rec[(kRecNu + d) * N + o]; }
+  __device__ R lb() const { return lb_; }
+  __device__ R nu() const { return nu_; }
   // Difference along the e-th tangential direction (in increasing direction order).
   __device__ R dt(int e, int v) const {
     const int dir = e == 0 ? (d == 0 ? 1 : 0) : (d == 2 ? 1 : 2);
@@ -262,6 +263,16 @@ struct GlobalNodeZ {
     if (e == 0) return (R)0.5 * (rec[(kRecU + v) * N + ip] - rec[(kRecU + v) * N + im]);
     return (R)0.5 * (rec[(kRecU + v) * N + jp] - rec[(kRecU + v) * N + jm]);
   }
+};
+
+// The same with the zeta scaled spectral radius and sensor prefetched by the caller.
+template <typename R>
+struct GlobalNodeZPre : GlobalNodeZ<R> {
+  R lb_, nu_;
+  __device__ GlobalNodeZPre(const StageArgs& A_, int i, int j, int k, R lb, R nu)
+      : GlobalNodeZ<R>(A_, i, j, k), lb_(lb), nu_(nu) {}
+  __device__ R lb() const { return lb_; }
+  __device__ R nu() const { return nu_; }
 };
 
 // Total numerical flux H = (F_A + F_B)/2 - D - F_v on a face along d (paper, Spatial
@@ -344,6 +355,9 @@ __device__ __forceinline__ void stage_block(const StageArgs& A, int bx, int by, 
   constexpr int M1 = (PL::N1 + NT - 1) / NT;
   constexpr int MX = (PL::NX + NT - 1) / NT;  // face slots per thread
   constexpr int MY = (PL::NY + NT - 1) / NT;
+  constexpr int NDX = (TX + 2) * TY, NDY = TX * (TY + 2);
+  constexpr int MDX = (NDX + NT - 1) / NT;  // lb/nu staging slots per thread
+  constexpr int MDY = (NDY + NT - 1) / NT;
   const Dims& D = A.D;
   const PhysT<R> Ph(A.P);
   const int N = (int)D.N;
@@ -423,6 +437,41 @@ __device__ __forceinline__ void stage_block(const StageArgs& A, int bx, int by, 
           vf[r][sDz + c] = (R)0.5 * (rec[(kRecU + c) * N + op] - rec[(kRecU + c) * N + om]);
       }
     }
+    // Scaled spectral radius and sensor of the xi- and eta-face nodes, and of the own
+    // column's zeta face (lower and upper node), loaded with the staging.
+    R vdx[MDX][2], vdy[MDY][2], zl[4] = {0, 0, 0, 0};
+#pragma unroll
+    for (int r = 0; r < MDX; ++r) {
+      const int s = tid + r * NT;
+      const int ia = wrap_or_out(i0 - 1 + s % (TX + 2), ni, D.per[0]);
+      const int ja = wrap_or_out(j0 + s / (TX + 2), nj, D.per[1]);
+      vdx[r][0] = vdx[r][1] = (R)0;
+      if (s < NDX && ia >= 0 && ja >= 0) {
+        const unsigned o = (unsigned)(ia + ni * (ja + nj * k));
+        vdx[r][0] = rec[kRecLb * N + o];
+        vdx[r][1] = rec[kRecNu * N + o];
+      }
+    }
+#pragma unroll
+    for (int r = 0; r < MDY; ++r) {
+      const int s = tid + r * NT;
+      const int ia = wrap_or_out(i0 + s % TX, ni, D.per[0]);
+      const int ja = wrap_or_out(j0 - 1 + s / TX, nj, D.per[1]);
+      vdy[r][0] = vdy[r][1] = (R)0;
+      if (s < NDY && ia >= 0 && ja >= 0) {
+        const unsigned o = (unsigned)(ia + ni * (ja + nj * k));
+        vdy[r][0] = rec[(kRecLb + 1) * N + o];
+        vdy[r][1] = rec[(kRecNu + 1) * N + o];
+      }
+    }
+    if (mine) {
+      const unsigned o = (unsigned)(i + ni * (j + nj * k));
+      const unsigned op = k + 1 == nk ? o - (unsigned)(nk - 1) * pl : o + pl;
+      zl[0] = rec[(kRecLb + 2) * N + o];
+      zl[1] = rec[(kRecNu + 2) * N + o];
+      zl[2] = rec[(kRecLb + 2) * N + op];
+      zl[3] = rec[(kRecNu + 2) * N + op];
+    }
     __syncthreads();  // the previous plane's face fluxes have been consumed
 #pragma unroll
     for (int r = 0; r < MW; ++r) {
@@ -438,6 +487,22 @@ __device__ __forceinline__ void stage_block(const StageArgs& A, int bx, int by, 
 #pragma unroll
         for (int c = 0; c < sNF; ++c) L.in.F[c][s] = vf[r][c];
     }
+#pragma unroll
+    for (int r = 0; r < MDX; ++r) {
+      const int s = tid + r * NT;
+      if (s < NDX) {
+        L.in.DX[0][s] = vdx[r][0];
+        L.in.DX[1][s] = vdx[r][1];
+      }
+    }
+#pragma unroll
+    for (int r = 0; r < MDY; ++r) {
+      const int s = tid + r * NT;
+      if (s < NDY) {
+        L.in.DY[0][s] = vdy[r][0];
+        L.in.DY[1][s] = vdy[r][1];
+      }
+    }
     __syncthreads();
 
     // Faces of the plane, held in registers until the staging space is free.
@@ -451,12 +516,12 @@ __device__ __forceinline__ void stage_block(const StageArgs& A, int bx, int by, 
       const int ia = wrap_or_out(i0 - 1 + fx, ni, D.per[0]);
       const int ja = wrap_or_out(j0 + fy, nj, D.per[1]);
       if (s < PL::NX && ia >= 0 && ja >= 0 && (D.per[0] || ia < ni - 1)) {
-        const unsigned oa = (unsigned)(ia + ni * (ja + nj * k));
-        const unsigned ob = ia + 1 == ni ? oa - (unsigned)(ni - 1) : oa + 1;
+        const int da = fx + (TX + 2) * fy;
         const LdsNode<TX, TY, 0, R> na{L, fx + PL::RX1 * (fy + 1), (fx + 1) + PL::RX2 * (fy + 2),
-                                       oa, rec, N};
+                                       L.in.DX[0][da], L.in.DX[1][da]};
         const LdsNode<TX, TY, 0, R> nb{L, fx + 1 + PL::RX1 * (fy + 1),
-                                       (fx + 2) + PL::RX2 * (fy + 2), ob, rec, N};
+                                       (fx + 2) + PL::RX2 * (fy + 2), L.in.DX[0][da + 1],
+                                       L.in.DX[1][da + 1]};
         R wm[5], wp[5];
 #pragma unroll
         for (int c = 0; c < 5; ++c) {
@@ -475,12 +540,12 @@ __device__ __forceinline__ void stage_block(const StageArgs& A, int bx, int by, 
       const int ia = wrap_or_out(i0 + fx, ni, D.per[0]);
       const int ja = wrap_or_out(j0 - 1 + fy, nj, D.per[1]);
       if (s < PL::NY && ia >= 0 && ja >= 0 && (D.per[1] || ja < nj - 1)) {
-        const unsigned oa = (unsigned)(ia + ni * (ja + nj * k));
-        const unsigned ob = ja + 1 == nj ? oa - (unsigned)((nj - 1) * ni) : oa + ni;
-        const LdsNode<TX, TY, 1, R> na{L, fx + 1 + PL::RX1 * fy, (fx + 2) + PL::RX2 * (fy + 1), oa,
-                                       rec, N};
+        const int da = fx + TX * fy;
+        const LdsNode<TX, TY, 1, R> na{L, fx + 1 + PL::RX1 * fy, (fx + 2) + PL::RX2 * (fy + 1),
+                                       L.in.DY[0][da], L.in.DY[1][da]};
         const LdsNode<TX, TY, 1, R> nb{L, fx + 1 + PL::RX1 * (fy + 1),
-                                       (fx + 2) + PL::RX2 * (fy + 2), ob, rec, N};
+                                       (fx + 2) + PL::RX2 * (fy + 2), L.in.DY[0][da + TX],
+                                       L.in.DY[1][da + TX]};
         R wm[5], wp[5];
 #pragma unroll
         for (int c = 0; c < 5; ++c) {
@@ -494,12 +559,11 @@ __device__ __forceinline__ void stage_block(const StageArgs& A, int bx, int by, 
     R hz[5] = {0, 0, 0, 0, 0};
     R Wcur[5] = {0, 0, 0, 0, 0};
     if (mine) {
-      const unsigned o = (unsigned)(i + ni * (j + nj * k));
-      const LdsNode<TX, TY, 2, R> na{L, a + 1 + PL::RX1 * (b + 1), (a + 2) + PL::RX2 * (b + 2), o,
-                                     rec, N};
+      const LdsNode<TX, TY, 2, R> na{L, a + 1 + PL::RX1 * (b + 1), (a + 2) + PL::RX2 * (b + 2),
+                                     zl[0], zl[1]};
       const int kp = k + 1 == nk ? 0 : k + 1;
       const int kp2 = kp + 1 == nk ? 0 : kp + 1;
-      const GlobalNodeZ<R> nb(A, i, j, kp);
+      const GlobalNodeZPre<R> nb(A, i, j, kp, zl[2], zl[3]);
       const unsigned o2 = (unsigned)(i + ni * (j + nj * kp2));
       R wp[5];
 #pragma unroll
@@ -593,7 +657,8 @@ hipError_t launch_nodes(const StageArgs& A, hipStream_t s) {
 }
 
 const char* const kTileNames[kNumTiles] = {"32x8", "32x4", "16x8", "16x16", "16x8/w2",
-                                           "16x16/w2"};
+                                           "16x16/w2", "32x8/w3", "16x16/w3", "32x8/w4",
+                                           "16x16/w4"};
 
 template <int TX, int TY, int WPE = 1, typename R = double>
 hipError_t launch_planes(const StageArgs& A, hipStream_t s, int kmin) {
@@ -605,7 +670,8 @@ hipError_t launch_planes(const StageArgs& A, hipStream_t s, int kmin) {
 }
 
 void tile_shape(int tile, int* tx, int* ty) {
-  static const int shapes[kNumTiles][2] = {{32, 8}, {32, 4}, {16, 8}, {16, 16}, {16, 8}, {16, 16}};
+  static const int shapes[kNumTiles][2] = {{32, 8}, {32, 4}, {16, 8}, {16, 16}, {16, 8},
+                                           {16, 16}, {32, 8}, {16, 16}, {32, 8}, {16, 16}};
   const int t = tile >= 0 && tile < kNumTiles ? tile : 0;
   *tx = shapes[t][0];
   *ty = shapes[t][1];
@@ -641,6 +707,10 @@ hipError_t batch_stage_tile(const BatchLaunch& B, hipStream_t s) {
     case 3: return batch_stage<16, 16, 1, R>(B, s);
     case 4: return batch_stage<16, 8, 2, R>(B, s);
     case 5: return batch_stage<16, 16, 2, R>(B, s);
+    case 6: return batch_stage<32, 8, 3, R>(B, s);
+    case 7: return batch_stage<16, 16, 3, R>(B, s);
+    case 8: return batch_stage<32, 8, 4, R>(B, s);
+    case 9: return batch_stage<16, 16, 4, R>(B, s);
     default: return batch_stage<32, 8, 1, R>(B, s);
   }
 }
@@ -677,6 +747,10 @@ hipError_t launch_stage(const StageArgs& A, hipStream_t s) {
       case 3: return launch_planes<16, 16, 1, float>(A, s, kmin);
       case 4: return launch_planes<16, 8, 2, float>(A, s, kmin);
       case 5: return launch_planes<16, 16, 2, float>(A, s, kmin);
+      case 6: return launch_planes<32, 8, 3, float>(A, s, kmin);
+      case 7: return launch_planes<16, 16, 3, float>(A, s, kmin);
+      case 8: return launch_planes<32, 8, 4, float>(A, s, kmin);
+      case 9: return launch_planes<16, 16, 4, float>(A, s, kmin);
       default: return launch_planes<32, 8, 1, float>(A, s, kmin);
     }
   switch (A.tile) {
@@ -685,6 +759,10 @@ hipError_t launch_stage(const StageArgs& A, hipStream_t s) {
     case 3: return launch_planes<16, 16>(A, s, kmin);
     case 4: return launch_planes<16, 8, 2>(A, s, kmin);
     case 5: return launch_planes<16, 16, 2>(A, s, kmin);
+    case 6: return launch_planes<32, 8, 3>(A, s, kmin);
+    case 7: return launch_planes<16, 16, 3>(A, s, kmin);
+    case 8: return launch_planes<32, 8, 4>(A, s, kmin);
+    case 9: return launch_planes<16, 16, 4>(A, s, kmin);
     default: return launch_planes<32, 8>(A, s, kmin);
   }
 }

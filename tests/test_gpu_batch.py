@@ -124,7 +124,7 @@ def test_batch_fixed_dt_and_tuning(torch):
         c.close()
     b = Batch(ctxs)
     start = [s.clone() for s in states]
-    for tile in range(6):
+    for tile in range(10):
         for kmin in (1, 5):
             for s, s0 in zip(states, start):
                 s.copy_(s0)
@@ -144,10 +144,10 @@ def test_autotuners_keep_state(torch):
     ctxs, states = _prepare(torch, members)
     before = [s.cpu().numpy() for s in states]
     t, k = ctxs[2].autotune(states[2])
-    assert 0 <= t < 6 and k in (4, 8, 16)
+    assert 0 <= t < 10 and k in (4, 8, 16)
     b = Batch(ctxs)
     t, k = b.autotune(states)
-    assert 0 <= t < 6 and k in (4, 8, 16)
+    assert 0 <= t < 10 and k in (4, 8, 16)
     assert b.get_tuning() == (t, k)
     for s, s0 in zip(states, before):
         assert np.array_equal(s.cpu().numpy(), s0)

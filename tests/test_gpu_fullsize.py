@@ -98,7 +98,7 @@ def test_tiles_bitwise_equal(torch, precision):
     g = torch.from_numpy(q).cuda()
     base = ctx.residual(g).cpu().numpy()
     names = ctx.tuning_names()
-    assert len(names) == 6
+    assert len(names) == 10
     for t in range(len(names)):
         for kmin in (1, 3, 8):
             ctx.set_tuning(t, kmin)
