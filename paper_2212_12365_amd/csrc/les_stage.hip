@@ -68,20 +68,20 @@ __device__ __forceinline__ R w_of(const StageArgs& A, unsigned o, int c, R prel)
 
 // Node record of one node. Primitive variables are formed in FP64 from the FP64 state;
 // the differences, eddy viscosity, spectral radii and sensors are evaluated in R.
-// One 64 x 4 block of nodes at (bx, by) in plane k.
-template <typename R>
-__device__ __forceinline__ void nodes_block(const StageArgs& A, int bx, int by, int k) {
+// Node record of node (i, j, k). With kQueue the primitive variables of the node and of its
+// zeta neighbours (periodic zeta) are given by the caller (zm, z0, zp); otherwise they are
+// loaded here.
+template <typename R, bool kQueue>
+__device__ __forceinline__ void node_record(const StageArgs& A, int i, int j, int k,
+                                            const Prim& zm, const Prim& z0, const Prim& zp) {
   const Dims& D = A.D;
   const PhysT<R> P(A.P);
-  int i = bx * 64 + threadIdx.x;
-  int j = by * 4 + threadIdx.y;
-  if (i >= D.n[0] || j >= D.n[1]) return;
   const int N = (int)D.N;
   const double* __restrict__ q = A.q;
   const R* __restrict__ Sm = metrics_of<R>(A);
   int ix[3] = {i, j, k};
   int o = off3(D, i, j, k);
-  Prim s = load_prim(q, N, o, A.P);
+  Prim s = kQueue ? z0 : load_prim(q, N, o, A.P);
   const R su = (R)s.u, sv = (R)s.v, sw = (R)s.w, sp = (R)s.p;
   // Velocity differences delta_e u_m (centred; one-sided at the ends of a non-periodic
   // direction) and pressure sensors along e.
@@ -91,7 +91,12 @@ __device__ __forceinline__ void nodes_block(const StageArgs& A, int bx, int by, 
     int n = D.n[e], m = ix[e];
     int stride = e == 0 ? 1 : (e == 1 ? D.n[0] : D.n[0] * D.n[1]);
     bool interior = D.per[e] || (m > 0 && m < n - 1);
-    if (interior) {
+    if (kQueue && e == 2) {
+      du[e][0] = (R)0.5 * ((R)zp.u - (R)zm.u);
+      du[e][1] = (R)0.5 * ((R)zp.v - (R)zm.v);
+      du[e][2] = (R)0.5 * ((R)zp.w - (R)zm.w);
+      nu[e] = sensor<R>((R)zm.p, sp, (R)zp.p);
+    } else if (interior) {
       int mp = m + 1 == n ? 0 : m + 1, mm = m == 0 ? n - 1 : m - 1;
       Prim a = load_prim(q, N, o + (mp - m) * stride, A.P);
       Prim b = load_prim(q, N, o + (mm - m) * stride, A.P);
@@ -148,6 +153,37 @@ __device__ __forceinline__ void nodes_block(const StageArgs& A, int bx, int by, 
     const R dl = jinv > (R)0 ? cbrt(jinv) : (R)0;
     if (A.fscale) A.fscale[o] = (float)((R)s.rho * dl * dl * smag);
     if (A.fsmag) A.fsmag[o] = (float)smag;
+  }
+}
+
+// One 64 x 4 block of nodes at (bx, by) in plane k.
+template <typename R>
+__device__ __forceinline__ void nodes_block(const StageArgs& A, int bx, int by, int k) {
+  const int i = bx * 64 + threadIdx.x, j = by * 4 + threadIdx.y;
+  if (i >= A.D.n[0] || j >= A.D.n[1]) return;
+  const Prim none{};
+  node_record<R, false>(A, i, j, k, none, none, none);
+}
+
+// Single-grid form marching each (i, j) column through a chunk of z-planes (z periodic):
+// the primitive variables of planes k-1, k, k+1 stay in registers, so each plane of the
+// state is read once per chunk for the zeta differences.
+template <typename R>
+__global__ void __launch_bounds__(256) k_nodes_march(StageArgs A, int kchunk) {
+  const Dims& D = A.D;
+  const int i = blockIdx.x * 64 + threadIdx.x, j = blockIdx.y * 4 + threadIdx.y;
+  if (i >= D.n[0] || j >= D.n[1]) return;
+  const int nk = D.n[2], N = (int)D.N;
+  const int kbeg = blockIdx.z * kchunk, kend = min(kbeg + kchunk, nk);
+  const int pl = D.n[0] * D.n[1];
+  const int o0 = i + D.n[0] * j;
+  Prim zm = load_prim(A.q, N, o0 + pl * (kbeg == 0 ? nk - 1 : kbeg - 1), A.P);
+  Prim z0 = load_prim(A.q, N, o0 + pl * kbeg, A.P);
+  for (int k = kbeg; k < kend; ++k) {
+    const Prim zp = load_prim(A.q, N, o0 + pl * (k + 1 == nk ? 0 : k + 1), A.P);
+    node_record<R, true>(A, i, j, k, zm, z0, zp);
+    zm = z0;
+    z0 = zp;
   }
 }
 
@@ -648,7 +684,18 @@ k_stage_batch(const StageArgs* __restrict__ args, const int4* __restrict__ work,
 
 hipError_t launch_nodes(const StageArgs& A, hipStream_t s) {
   dim3 block(64, 4, 1);
-  dim3 grid((A.D.n[0] + 63) / 64, (A.D.n[1] + 3) / 4, A.D.n[2]);
+  const int gx = (A.D.n[0] + 63) / 64, gy = (A.D.n[1] + 3) / 4;
+  if (A.D.per[2]) {  // march through z-chunks of about 8 planes, at least 2048 blocks in all
+    const int nz = std::max(1, std::min(A.D.n[2], std::max(A.D.n[2] / 8, 2048 / (gx * gy))));
+    const int kchunk = (A.D.n[2] + nz - 1) / nz;
+    const dim3 grid(gx, gy, (A.D.n[2] + kchunk - 1) / kchunk);
+    if (A.mixed)
+      hipLaunchKernelGGL(k_nodes_march<float>, grid, block, 0, s, A, kchunk);
+    else
+      hipLaunchKernelGGL(k_nodes_march<double>, grid, block, 0, s, A, kchunk);
+    return hipGetLastError();
+  }
+  dim3 grid(gx, gy, A.D.n[2]);
   if (A.mixed)
     hipLaunchKernelGGL(k_nodes<float>, grid, block, 0, s, A);
   else
