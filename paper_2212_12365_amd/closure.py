@@ -114,3 +114,112 @@ def stack(snaps, key):
     if key == "feat":
         return torch.cat([d["feat"].reshape(6, -1) for d in snaps], dim=1).contiguous()
     return torch.cat([d[key].reshape(-1) for d in snaps]).contiguous()
+
+
+def aposteriori(fine, coarse, xyzc, q_fine, q_start, theta, norm, fine_steps, smin,
+                log=print):
+    """A-posteriori comparison: from the filtered state q_start, coarse runs (mixed form)
+    with the Smagorinsky closure and with the learned closure advance over the time the fine
+    run advances in `fine_steps` steps (coarse dt = 2 x the fine run's dt, fixed), and their
+    velocity fields are compared with the filtered fine solution at that time."""
+    import torch
+    from .lesmi import Context
+    dt_f = fine.step(q_fine, 1, cfl=0.5)
+    fine.step(q_fine, fine_steps - 1, cfl=0.0, dt_fixed=dt_f)
+    ref = lesmi.filter_target(fine, coarse, q_fine, smin)["q"]
+    coarse_params = coarse.params
+    u_ref = ref[1:4] / ref[0]
+    out = {"fine_dt": dt_f, "coarse_steps": fine_steps // 2}
+    for name, closure_id in (("smagorinsky", 0), ("learned", 1)):
+        c = Context(coarse_params.replace(precision=1, closure=closure_id), xyzc)
+        if closure_id == 1:
+            c.mlp_set_network(theta, norm)
+        g = q_start.clone()
+        c.apply_bc(g)
+        c.step(g, fine_steps // 2, cfl=0.0, dt_fixed=2.0 * dt_f)
+        u = g[1:4] / g[0]
+        inner = (slice(None), slice(None), slice(1, -1), slice(1, -1))
+        err = torch.linalg.vector_norm((u - u_ref)[inner]) / torch.linalg.vector_norm(u_ref[inner])
+        out[f"u_rel_l2_{name}"] = float(err)
+        if closure_id == 1:
+            out["fallback_evaluations"] = c.mlp_fallback_count()
+        c.close()
+        log(f"a-posteriori {name}: u rel-L2 vs filtered fine {float(err):.4e}")
+    return out
+
+
+def run(fine_shape=(768, 384, 384), spinup=1200, every=200, count=3, steps=600, batch=8192,
+        lr=2e-3, seed=0, smin=1.0, post_steps=400, log=print):
+    """End-to-end training of the closure on the jet: an FP64 run on the fine grid (seeded
+    jet field), `count` snapshots box-filtered onto the grid of half the nodes per direction,
+    training on all but the last snapshot and evaluation on the last; then, if post_steps > 0,
+    the a-posteriori comparison over post_steps fine steps. Returns a dict."""
+    import time as _time
+    import torch
+    import synthetic as sy
+    from .lesmi import Context
+    t0 = _time.perf_counter()
+    fine_shape = tuple(fine_shape)
+    coarse_shape = tuple(n // 2 for n in fine_shape)
+    pf, xyzf, qf = sy.make_case("jet", fine_shape, seed=seed)
+    xyzc = np.ascontiguousarray(xyzf.reshape(3, coarse_shape[2], 2, coarse_shape[1], 2,
+                                             coarse_shape[0], 2).mean(axis=(2, 4, 6)))
+    fine = Context(pf, xyzf)
+    coarse = Context(sy.jet_params(coarse_shape), xyzc)
+    del xyzf
+    g = torch.from_numpy(qf).cuda()
+    del qf
+    fine.apply_bc(g)
+    log(f"fine {fine_shape} ready in {_time.perf_counter() - t0:.1f} s")
+    t1 = _time.perf_counter()
+    done = 0
+    while done < spinup:
+        n = min(100, spinup - done)
+        fine.step(g, n, cfl=0.5)
+        done += n
+        log(f"fine run: {done}/{spinup} steps")
+    snaps = []
+    for c in range(count):
+        fine.step(g, every, cfl=0.5)
+        snaps.append(lesmi.filter_target(fine, coarse, g, smin))
+        log(f"snapshot {c + 1}/{count} after {spinup + (c + 1) * every} steps")
+    t_run = _time.perf_counter() - t1
+    cs2 = coarse.params.cs ** 2
+    train_snaps, test = snaps[:-1], snaps[-1]
+    t2 = _time.perf_counter()
+    theta, norm, losses = train(stack(train_snaps, "feat"), stack(train_snaps, "target"),
+                                stack(train_snaps, "weight"), cs2, steps=steps, batch=batch,
+                                lr=lr, seed=seed, log_every=max(steps // 6, 1))
+    torch.cuda.synchronize()
+    t_train = _time.perf_counter() - t2
+    res = evaluate(theta, norm, cs2, test["feat"], test["smag"], test["target"], test["weight"])
+    res.update({"fine_grid": list(fine_shape), "coarse_grid": list(coarse_shape),
+                "fine_steps": spinup + count * every, "snapshot_every": every,
+                "train_snapshots": count - 1, "adam_steps": steps, "batch": batch,
+                "losses": losses, "fine_run_s": round(t_run, 1), "train_s": round(t_train, 2)})
+    if post_steps > 0:
+        res["aposteriori"] = aposteriori(fine, coarse, xyzc, g, test["q"], theta, norm,
+                                         post_steps, smin, log)
+    fine.close()
+    coarse.close()
+    return res
+
+
+if __name__ == "__main__":
+    import argparse
+    import json
+    import os
+    import sys
+    sys.path.insert(0, os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
+    ap = argparse.ArgumentParser(description="train the learned closure on a filtered fine run")
+    ap.add_argument("--fine", default="768,384,384")
+    ap.add_argument("--spinup", type=int, default=1200)
+    ap.add_argument("--every", type=int, default=200)
+    ap.add_argument("--count", type=int, default=3)
+    ap.add_argument("--steps", type=int, default=600)
+    ap.add_argument("--batch", type=int, default=8192)
+    ap.add_argument("--post-steps", type=int, default=400)
+    a = ap.parse_args()
+    out = run(tuple(int(x) for x in a.fine.split(",")), a.spinup, a.every, a.count, a.steps,
+              a.batch, post_steps=a.post_steps, log=lambda m: print(m, flush=True))
+    print(json.dumps(out), flush=True)
