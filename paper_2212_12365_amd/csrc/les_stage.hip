@@ -354,6 +354,7 @@ __device__ __forceinline__ void face_eval(const NA& a, const NB& b, const R* Wm,
     for (int c = 0; c < 5; ++c) H[c] = H[c] - Dd[c];
   }
   {  // viscous and subgrid part
+#pragma clang fp contract(fast)
     R Sf[9];
 #pragma unroll
     for (int c = 0; c < 9; ++c) Sf[c] = (R)0.5 * (a.S(c) + b.S(c));
