@@ -128,7 +128,6 @@ __device__ __forceinline__ void inviscid_flux(double sx, double sy, double sz, c
 template <typename R, typename PP>
 __device__ __forceinline__ void dissipation(R lf, R nuA, R nuB, const R* dW, const R* d3W,
                                             const PP& P, R* D) {
-#pragma clang fp contract(fast)
   R eps2 = (R)P.k2 * (nuA > nuB ? nuA : nuB);
   R eps4 = (R)P.k4 - eps2;
   eps4 = eps4 > (R)0 ? eps4 : (R)0;
@@ -144,7 +143,6 @@ __device__ __forceinline__ void dissipation(R lf, R nuA, R nuB, const R* dW, con
 template <typename R, typename PP>
 __device__ __forceinline__ void viscous_flux(const R* Sf, R jinvf, const R gxi[4][3], R muf,
                                              R mutf, const R* ub, int d, const PP& P, R* F) {
-#pragma clang fp contract(fast)
   R Jf = (R)1 / jinvf;
   R g[4][3];  // d(var)/dx_n
 #pragma unroll

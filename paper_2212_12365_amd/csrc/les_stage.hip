@@ -301,14 +301,60 @@ struct GlobalNodeZ {
   }
 };
 
-// The same with the zeta scaled spectral radius and sensor prefetched by the caller.
-template <typename R>
-struct GlobalNodeZPre : GlobalNodeZ<R> {
-  R lb_, nu_;
-  __device__ GlobalNodeZPre(const StageArgs& A_, int i, int j, int k, R lb, R nu)
-      : GlobalNodeZ<R>(A_, i, j, k), lb_(lb), nu_(nu) {}
+// Face inputs of one node held in registers: the lower node of a zeta face, taken from
+// LDS while its own plane is staged and used when the plane above is staged. With kMetRegs
+// false the metrics and J^-1 are read again from global memory at the point of use (FP64,
+// where registers are short).
+template <typename R, bool kMetRegs>
+struct RegNode {
+  R w[5], pp, fv[4], mu_, mut_, s[kMetRegs ? 9 : 1], ji, d[2][4], lb_, nu_;
+  const R* Sm;
+  const double* jg;
+  unsigned o;
+  int N;
+  __device__ R W(int c) const { return w[c]; }
+  __device__ R p() const { return pp; }
+  __device__ R f(int v) const { return fv[v]; }
+  __device__ R mu() const { return mu_; }
+  __device__ R mut() const { return mut_; }
+  __device__ R S(int c) const {
+    if constexpr (kMetRegs) return s[c];
+    else return Sm[c * N + o];
+  }
+  __device__ R jinv() const {
+    if constexpr (kMetRegs) return ji;
+    else return (R)jg[o];
+  }
   __device__ R lb() const { return lb_; }
   __device__ R nu() const { return nu_; }
+  __device__ R dt(int e, int v) const { return d[e][v]; }
+  // Takes the inputs of node offset o_ from accessor n.
+  template <typename NodeT>
+  __device__ __forceinline__ void take(const NodeT& n, const StageArgs& A, unsigned o_) {
+#pragma unroll
+    for (int c = 0; c < 5; ++c) w[c] = n.W(c);
+    pp = n.p();
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      fv[v] = n.f(v);
+      d[0][v] = n.dt(0, v);
+      d[1][v] = n.dt(1, v);
+    }
+    mu_ = n.mu();
+    mut_ = n.mut();
+    if constexpr (kMetRegs) {
+#pragma unroll
+      for (int c = 0; c < 9; ++c) s[c] = n.S(c);
+      ji = n.jinv();
+    } else {
+      Sm = metrics_of<R>(A);
+      jg = A.jinv;
+      o = o_;
+      N = (int)A.D.N;
+    }
+    lb_ = n.lb();
+    nu_ = n.nu();
+  }
 };
 
 // Total numerical flux H = (F_A + F_B)/2 - D - F_v on a face along d (paper, Spatial
@@ -354,7 +400,6 @@ __device__ __forceinline__ void face_eval(const NA& a, const NB& b, const R* Wm,
     for (int c = 0; c < 5; ++c) H[c] = H[c] - Dd[c];
   }
   {  // viscous and subgrid part
-#pragma clang fp contract(fast)
     R Sf[9];
 #pragma unroll
     for (int c = 0; c < 9; ++c) Sf[c] = (R)0.5 * (a.S(c) + b.S(c));
@@ -379,10 +424,42 @@ __device__ __forceinline__ void face_eval(const NA& a, const NB& b, const R* Wm,
   }
 }
 
+// Residual of node (i, j, k) from the sum of its xi and eta face differences (part) and its
+// zeta faces above (hu) and below (hd): written out (mode 0) or applied as the Runge-Kutta
+// stage update Q = Q0 - alpha dt J R (mode 1). Nodes that are not updated get a zero
+// residual in mode 0 and are left alone in mode 1.
+template <typename R>
+__device__ __forceinline__ void finish_node(const StageArgs& A, int i, int j, int k,
+                                            const R* part, const R* hu, const R* hd) {
+  const Dims& D = A.D;
+  const int N = (int)D.N;
+  const int o = i + D.n[0] * (j + D.n[1] * k);
+  if (is_updated(D, i, j, k)) {
+    double fac = 0.0;
+    if (A.mode == 1) fac = A.alpha * A.dt[0] * A.jac[o];
+#pragma unroll
+    for (int c = 0; c < 5; ++c) {
+      R rr = part[c];
+      rr += hu[c] - hd[c];
+      if (A.mode == 0)
+        A.out[c * N + o] = (double)rr;
+      else
+        A.out[c * N + o] = A.q0[c * N + o] - fac * (double)rr;
+    }
+  } else if (A.mode == 0) {
+#pragma unroll
+    for (int c = 0; c < 5; ++c) A.out[c * N + o] = 0.0;
+  }
+}
+
 // One block per TX x TY column tile marches a chunk of z-planes (z is periodic). R is the
 // arithmetic type of the fluxes (double; float in the mixed form, where the state, the
 // Runge-Kutta update, J^-1 and J stay FP64).
 // Column tile (bx, by) over the z-planes kbeg .. kend-1, with the block's LDS L.
+// The zeta face between planes k-1 and k is evaluated while plane k is staged: its upper node
+// comes from LDS and its lower node from registers (taken from LDS one plane earlier), so the
+// update of the column's node on plane k-1 completes one plane late. The faces below the
+// first and above the last plane of the chunk read their outer node from global memory.
 template <int TX, int TY, typename R>
 __device__ __forceinline__ void stage_block(const StageArgs& A, int bx, int by, int kbeg,
                                             int kend, PlaneLds<TX, TY, R>& L) {
@@ -409,10 +486,13 @@ __device__ __forceinline__ void stage_block(const StageArgs& A, int bx, int by, 
   const R* __restrict__ S = metrics_of<R>(A);
   const unsigned pl = (unsigned)(ni * nj);
 
-  // Zeta face below the chunk, and the dissipated vector one plane below the current one.
+  // State of the column between planes: the zeta face below the pending node (hz_lo), the
+  // pending node's xi/eta flux sum (part) and face inputs (lo), and W one plane below it.
   R hz_lo[5] = {0, 0, 0, 0, 0};
-  R Wlow[5] = {0, 0, 0, 0, 0};
-  if (mine) {
+  R Wm[5] = {0, 0, 0, 0, 0};
+  R part[5] = {0, 0, 0, 0, 0};
+  RegNode<R, sizeof(R) == sizeof(float)> lo;
+  if (mine) {  // zeta face below the chunk
     const int kl = kbeg == 0 ? nk - 1 : kbeg - 1;
     const int kl2 = kl == 0 ? nk - 1 : kl - 1;
     const GlobalNodeZ<R> na(A, i, j, kl), nb(A, i, j, kbeg);
@@ -427,126 +507,166 @@ __device__ __forceinline__ void stage_block(const StageArgs& A, int bx, int by, 
     }
     face_eval<2, R>(na, nb, wm, wp, kl, nk, true, Ph, hz_lo);
 #pragma unroll
-    for (int c = 0; c < 5; ++c) Wlow[c] = na.W(c);
+    for (int c = 0; c < 5; ++c) Wm[c] = na.W(c);
   }
 
   for (int k = kbeg; k < kend; ++k) {
-    // Every staging load of the plane in flight at once.
-    R vw[MW][6];
-    R vf[M1][sNF];
-#pragma unroll
-    for (int r = 0; r < MW; ++r) {
-      const int s = tid + r * NT;
+    const bool pending = mine && k > kbeg;  // the node on plane k-1 awaits its upper face
+    // The thread index passed through an empty asm statement: the staging addresses derived
+    // from it are then formed anew on each plane instead of being hoisted out of the loop
+    // (where they would hold registers across the face arithmetic).
+    int tl = tid;
+    asm volatile("" : "+v"(tl));
+    // Staging loads of slot s of the two-node ring (W and p) and of the one-node ring (the
+    // other face inputs); nodes outside a non-periodic range stage zeros.
+    auto load_w = [&](int s, R(&v)[6]) {
       const int ia = wrap_or_out(i0 - 2 + s % PL::RX2, ni, D.per[0]);
       const int ja = wrap_or_out(j0 - 2 + s / PL::RX2, nj, D.per[1]);
 #pragma unroll
-      for (int c = 0; c < 6; ++c) vw[r][c] = (R)0;
+      for (int c = 0; c < 6; ++c) v[c] = (R)0;
       if (s < PL::NW && ia >= 0 && ja >= 0) {
         const unsigned o = (unsigned)(ia + ni * (ja + nj * k));
         const R pr = rec[kRecP * N + o];
 #pragma unroll
-        for (int c = 0; c < 5; ++c) vw[r][c] = w_of<R>(A, o, c, pr);
-        vw[r][5] = pr;
+        for (int c = 0; c < 5; ++c) v[c] = w_of<R>(A, o, c, pr);
+        v[5] = pr;
       }
-    }
-#pragma unroll
-    for (int r = 0; r < M1; ++r) {
-      const int s = tid + r * NT;
+    };
+    auto load_f = [&](int s, R(&v)[sNF]) {
       const int ia = wrap_or_out(i0 - 1 + s % PL::RX1, ni, D.per[0]);
       const int ja = wrap_or_out(j0 - 1 + s / PL::RX1, nj, D.per[1]);
 #pragma unroll
-      for (int c = 0; c < sNF; ++c) vf[r][c] = (R)0;
+      for (int c = 0; c < sNF; ++c) v[c] = (R)0;
       if (s < PL::N1 && ia >= 0 && ja >= 0) {
         const unsigned o = (unsigned)(ia + ni * (ja + nj * k));
-        vf[r][sU] = rec[kRecU * N + o];
-        vf[r][sV] = rec[kRecV * N + o];
-        vf[r][sWv] = rec[kRecW * N + o];
-        vf[r][sT] = rec[kRecT * N + o];
-        vf[r][sMu] = rec[kRecMu * N + o];
-        vf[r][sMut] = rec[kRecMut * N + o];
+        v[sU] = rec[kRecU * N + o];
+        v[sV] = rec[kRecV * N + o];
+        v[sWv] = rec[kRecW * N + o];
+        v[sT] = rec[kRecT * N + o];
+        v[sMu] = rec[kRecMu * N + o];
+        v[sMut] = rec[kRecMut * N + o];
 #pragma unroll
-        for (int c = 0; c < 9; ++c) vf[r][sS0 + c] = S[c * N + o];
-        vf[r][sJinv] = (R)A.jinv[o];
+        for (int c = 0; c < 9; ++c) v[sS0 + c] = S[c * N + o];
+        v[sJinv] = (R)A.jinv[o];
         const unsigned op = k + 1 == nk ? o - (unsigned)(nk - 1) * pl : o + pl;
         const unsigned om = k == 0 ? o + (unsigned)(nk - 1) * pl : o - pl;
 #pragma unroll
         for (int c = 0; c < 4; ++c)
-          vf[r][sDz + c] = (R)0.5 * (rec[(kRecU + c) * N + op] - rec[(kRecU + c) * N + om]);
+          v[sDz + c] = (R)0.5 * (rec[(kRecU + c) * N + op] - rec[(kRecU + c) * N + om]);
       }
-    }
-    // Scaled spectral radius and sensor of the xi- and eta-face nodes, and of the own
-    // column's zeta face (lower and upper node), loaded with the staging.
-    R vdx[MDX][2], vdy[MDY][2], zl[4] = {0, 0, 0, 0};
+    };
+    // The plane is staged in two groups of loads, each written to LDS as it arrives.
+    // Group 1: the two-node ring, the first slot of the one-node ring, the own node's zeta
+    // spectral radius and sensor, and W one plane above the own node (outer node of the
+    // pending zeta face).
+    R zl[2] = {0, 0}, wp[5] = {0, 0, 0, 0, 0};
+    {
+      R vw[MW][6], vf[sNF];
 #pragma unroll
-    for (int r = 0; r < MDX; ++r) {
-      const int s = tid + r * NT;
-      const int ia = wrap_or_out(i0 - 1 + s % (TX + 2), ni, D.per[0]);
-      const int ja = wrap_or_out(j0 + s / (TX + 2), nj, D.per[1]);
-      vdx[r][0] = vdx[r][1] = (R)0;
-      if (s < NDX && ia >= 0 && ja >= 0) {
-        const unsigned o = (unsigned)(ia + ni * (ja + nj * k));
-        vdx[r][0] = rec[kRecLb * N + o];
-        vdx[r][1] = rec[kRecNu * N + o];
+      for (int r = 0; r < MW; ++r) load_w(tl + r * NT, vw[r]);
+      load_f(tl, vf);
+      if (mine) {
+        const unsigned o = (unsigned)(i + ni * (j + nj * k));
+        zl[0] = rec[(kRecLb + 2) * N + o];
+        zl[1] = rec[(kRecNu + 2) * N + o];
       }
-    }
+      if (pending) {
+        const int kp = k + 1 == nk ? 0 : k + 1;
+        const unsigned o2 = (unsigned)(i + ni * (j + nj * kp));
 #pragma unroll
-    for (int r = 0; r < MDY; ++r) {
-      const int s = tid + r * NT;
-      const int ia = wrap_or_out(i0 + s % TX, ni, D.per[0]);
-      const int ja = wrap_or_out(j0 - 1 + s / TX, nj, D.per[1]);
-      vdy[r][0] = vdy[r][1] = (R)0;
-      if (s < NDY && ia >= 0 && ja >= 0) {
-        const unsigned o = (unsigned)(ia + ni * (ja + nj * k));
-        vdy[r][0] = rec[(kRecLb + 1) * N + o];
-        vdy[r][1] = rec[(kRecNu + 1) * N + o];
+        for (int c = 0; c < 5; ++c)
+          wp[c] = w_of<R>(A, o2, c, c == 4 ? rec[kRecP * N + o2] : (R)0);
       }
-    }
-    if (mine) {
-      const unsigned o = (unsigned)(i + ni * (j + nj * k));
-      const unsigned op = k + 1 == nk ? o - (unsigned)(nk - 1) * pl : o + pl;
-      zl[0] = rec[(kRecLb + 2) * N + o];
-      zl[1] = rec[(kRecNu + 2) * N + o];
-      zl[2] = rec[(kRecLb + 2) * N + op];
-      zl[3] = rec[(kRecNu + 2) * N + op];
-    }
-    __syncthreads();  // the previous plane's face fluxes have been consumed
 #pragma unroll
-    for (int r = 0; r < MW; ++r) {
-      const int s = tid + r * NT;
-      if (s < PL::NW)
+      for (int r = 0; r < MW; ++r) {
+        const int s = tl + r * NT;
+        if (s < PL::NW)
 #pragma unroll
-        for (int c = 0; c < 6; ++c) L.in.W[c][s] = vw[r][c];
-    }
-#pragma unroll
-    for (int r = 0; r < M1; ++r) {
-      const int s = tid + r * NT;
-      if (s < PL::N1)
-#pragma unroll
-        for (int c = 0; c < sNF; ++c) L.in.F[c][s] = vf[r][c];
-    }
-#pragma unroll
-    for (int r = 0; r < MDX; ++r) {
-      const int s = tid + r * NT;
-      if (s < NDX) {
-        L.in.DX[0][s] = vdx[r][0];
-        L.in.DX[1][s] = vdx[r][1];
+          for (int c = 0; c < 6; ++c) L.in.W[c][s] = vw[r][c];
       }
-    }
+      if (tl < PL::N1)
 #pragma unroll
-    for (int r = 0; r < MDY; ++r) {
-      const int s = tid + r * NT;
-      if (s < NDY) {
-        L.in.DY[0][s] = vdy[r][0];
-        L.in.DY[1][s] = vdy[r][1];
+        for (int c = 0; c < sNF; ++c) L.in.F[c][tl] = vf[c];
+    }
+    // Group 2: the other slots of the one-node ring, and the scaled spectral radius and
+    // sensor of the xi- and eta-face nodes.
+    {
+      constexpr int M1b = M1 > 1 ? M1 - 1 : 1;
+      R vf[M1b][sNF], vdx[MDX][2], vdy[MDY][2];
+#pragma unroll
+      for (int r = 1; r < M1; ++r) load_f(tl + r * NT, vf[r - 1]);
+#pragma unroll
+      for (int r = 0; r < MDX; ++r) {
+        const int s = tl + r * NT;
+        const int ia = wrap_or_out(i0 - 1 + s % (TX + 2), ni, D.per[0]);
+        const int ja = wrap_or_out(j0 + s / (TX + 2), nj, D.per[1]);
+        vdx[r][0] = vdx[r][1] = (R)0;
+        if (s < NDX && ia >= 0 && ja >= 0) {
+          const unsigned o = (unsigned)(ia + ni * (ja + nj * k));
+          vdx[r][0] = rec[kRecLb * N + o];
+          vdx[r][1] = rec[kRecNu * N + o];
+        }
+      }
+#pragma unroll
+      for (int r = 0; r < MDY; ++r) {
+        const int s = tl + r * NT;
+        const int ia = wrap_or_out(i0 + s % TX, ni, D.per[0]);
+        const int ja = wrap_or_out(j0 - 1 + s / TX, nj, D.per[1]);
+        vdy[r][0] = vdy[r][1] = (R)0;
+        if (s < NDY && ia >= 0 && ja >= 0) {
+          const unsigned o = (unsigned)(ia + ni * (ja + nj * k));
+          vdy[r][0] = rec[(kRecLb + 1) * N + o];
+          vdy[r][1] = rec[(kRecNu + 1) * N + o];
+        }
+      }
+#pragma unroll
+      for (int r = 1; r < M1; ++r) {
+        const int s = tl + r * NT;
+        if (s < PL::N1)
+#pragma unroll
+          for (int c = 0; c < sNF; ++c) L.in.F[c][s] = vf[r - 1][c];
+      }
+#pragma unroll
+      for (int r = 0; r < MDX; ++r) {
+        const int s = tl + r * NT;
+        if (s < NDX) {
+          L.in.DX[0][s] = vdx[r][0];
+          L.in.DX[1][s] = vdx[r][1];
+        }
+      }
+#pragma unroll
+      for (int r = 0; r < MDY; ++r) {
+        const int s = tl + r * NT;
+        if (s < NDY) {
+          L.in.DY[0][s] = vdy[r][0];
+          L.in.DY[1][s] = vdy[r][1];
+        }
       }
     }
     __syncthreads();
+
+    // Zeta face between planes k-1 and k, and the update of the node on plane k-1.
+    int tf = tid;  // laundered again for the face phase
+    asm volatile("" : "+v"(tf));
+    const int own1 = tf % TX + 1 + PL::RX1 * (tf / TX + 1);
+    const int own2 = tf % TX + 2 + PL::RX2 * (tf / TX + 2);
+    if (pending) {
+      const LdsNode<TX, TY, 2, R> nb{L, own1, own2, zl[0], zl[1]};
+      R hz[5];
+      face_eval<2, R>(lo, nb, Wm, wp, k - 1, nk, true, Ph, hz);
+      finish_node<R>(A, i, j, k - 1, part, hz, hz_lo);
+#pragma unroll
+      for (int c = 0; c < 5; ++c) {
+        hz_lo[c] = hz[c];
+        Wm[c] = lo.w[c];
+      }
+    }
 
     // Faces of the plane, held in registers until the staging space is free.
     R hx[MX][5], hy[MY][5];
 #pragma unroll
     for (int r = 0; r < MX; ++r) {
-      const int s = tid + r * NT;
+      const int s = tf + r * NT;
 #pragma unroll
       for (int c = 0; c < 5; ++c) hx[r][c] = (R)0;
       const int fx = s % (TX + 1), fy = s / (TX + 1);
@@ -559,18 +679,18 @@ __device__ __forceinline__ void stage_block(const StageArgs& A, int bx, int by, 
         const LdsNode<TX, TY, 0, R> nb{L, fx + 1 + PL::RX1 * (fy + 1),
                                        (fx + 2) + PL::RX2 * (fy + 2), L.in.DX[0][da + 1],
                                        L.in.DX[1][da + 1]};
-        R wm[5], wp[5];
+        R wm[5], wq[5];
 #pragma unroll
         for (int c = 0; c < 5; ++c) {
           wm[c] = L.in.W[c][fx + PL::RX2 * (fy + 2)];
-          wp[c] = L.in.W[c][fx + 3 + PL::RX2 * (fy + 2)];
+          wq[c] = L.in.W[c][fx + 3 + PL::RX2 * (fy + 2)];
         }
-        face_eval<0, R>(na, nb, wm, wp, ia, ni, D.per[0], Ph, hx[r]);
+        face_eval<0, R>(na, nb, wm, wq, ia, ni, D.per[0], Ph, hx[r]);
       }
     }
 #pragma unroll
     for (int r = 0; r < MY; ++r) {
-      const int s = tid + r * NT;
+      const int s = tf + r * NT;
 #pragma unroll
       for (int c = 0; c < 5; ++c) hy[r][c] = (R)0;
       const int fx = s % TX, fy = s / TX;
@@ -583,75 +703,57 @@ __device__ __forceinline__ void stage_block(const StageArgs& A, int bx, int by, 
         const LdsNode<TX, TY, 1, R> nb{L, fx + 1 + PL::RX1 * (fy + 1),
                                        (fx + 2) + PL::RX2 * (fy + 2), L.in.DY[0][da + TX],
                                        L.in.DY[1][da + TX]};
-        R wm[5], wp[5];
+        R wm[5], wq[5];
 #pragma unroll
         for (int c = 0; c < 5; ++c) {
           wm[c] = L.in.W[c][fx + 2 + PL::RX2 * fy];
-          wp[c] = L.in.W[c][fx + 2 + PL::RX2 * (fy + 3)];
+          wq[c] = L.in.W[c][fx + 2 + PL::RX2 * (fy + 3)];
         }
-        face_eval<1, R>(na, nb, wm, wp, ja, nj, D.per[1], Ph, hy[r]);
+        face_eval<1, R>(na, nb, wm, wq, ja, nj, D.per[1], Ph, hy[r]);
       }
     }
-    // Zeta face above the own node: lower node from LDS, upper node from global memory.
-    R hz[5] = {0, 0, 0, 0, 0};
-    R Wcur[5] = {0, 0, 0, 0, 0};
-    if (mine) {
-      const LdsNode<TX, TY, 2, R> na{L, a + 1 + PL::RX1 * (b + 1), (a + 2) + PL::RX2 * (b + 2),
-                                     zl[0], zl[1]};
-      const int kp = k + 1 == nk ? 0 : k + 1;
-      const int kp2 = kp + 1 == nk ? 0 : kp + 1;
-      const GlobalNodeZPre<R> nb(A, i, j, kp, zl[2], zl[3]);
-      const unsigned o2 = (unsigned)(i + ni * (j + nj * kp2));
-      R wp[5];
-#pragma unroll
-      for (int c = 0; c < 5; ++c) wp[c] = w_of<R>(A, o2, c, c == 4 ? rec[kRecP * N + o2] : (R)0);
-      face_eval<2, R>(na, nb, Wlow, wp, k, nk, true, Ph, hz);
-#pragma unroll
-      for (int c = 0; c < 5; ++c) Wcur[c] = na.W(c);
-    }
+    // The own node becomes the lower node of the next zeta face.
+    if (mine)
+      lo.take(LdsNode<TX, TY, 2, R>{L, own1, own2, zl[0], zl[1]}, A,
+              (unsigned)(i + ni * (j + nj * k)));
     __syncthreads();  // staging reads done: the space now takes the face fluxes
 #pragma unroll
     for (int r = 0; r < MX; ++r) {
-      const int s = tid + r * NT;
+      const int s = tf + r * NT;
       if (s < PL::NX)
 #pragma unroll
         for (int c = 0; c < 5; ++c) L.H[c][s] = hx[r][c];
     }
 #pragma unroll
     for (int r = 0; r < MY; ++r) {
-      const int s = tid + r * NT;
+      const int s = tf + r * NT;
       if (s < PL::NY)
 #pragma unroll
         for (int c = 0; c < 5; ++c) L.H[c][PL::NX + s] = hy[r][c];
     }
     __syncthreads();
     if (mine) {
-      const int o = i + ni * (j + nj * k);
-      if (is_updated(D, i, j, k)) {
-        const int sx = a + (TX + 1) * b, sy = PL::NX + a + TX * b;
-        double fac = 0.0;
-        if (A.mode == 1) fac = A.alpha * A.dt[0] * A.jac[o];
-#pragma unroll
-        for (int c = 0; c < 5; ++c) {
-          R rr = (R)0;
-          rr += L.H[c][sx + 1] - L.H[c][sx];
-          rr += L.H[c][sy + TX] - L.H[c][sy];
-          rr += hz[c] - hz_lo[c];
-          if (A.mode == 0)
-            A.out[c * N + o] = (double)rr;
-          else
-            A.out[c * N + o] = A.q0[c * N + o] - fac * (double)rr;
-        }
-      } else if (A.mode == 0) {
-#pragma unroll
-        for (int c = 0; c < 5; ++c) A.out[c * N + o] = 0.0;
-      }
+      const int sx = a + (TX + 1) * b, sy = PL::NX + a + TX * b;
 #pragma unroll
       for (int c = 0; c < 5; ++c) {
-        hz_lo[c] = hz[c];
-        Wlow[c] = Wcur[c];
+        R rr = (R)0;
+        rr += L.H[c][sx + 1] - L.H[c][sx];
+        rr += L.H[c][sy + TX] - L.H[c][sy];
+        part[c] = rr;
       }
     }
+    __syncthreads();  // the face fluxes have been consumed: the space takes the next plane
+  }
+  if (mine && kend > kbeg) {  // zeta face above the chunk, upper node from global memory
+    const int kt = kend == nk ? 0 : kend;
+    const int kt2 = kt + 1 == nk ? 0 : kt + 1;
+    const GlobalNodeZ<R> nb(A, i, j, kt);
+    const unsigned o2 = (unsigned)(i + ni * (j + nj * kt2));
+    R wp[5], hz[5];
+#pragma unroll
+    for (int c = 0; c < 5; ++c) wp[c] = w_of<R>(A, o2, c, c == 4 ? rec[kRecP * N + o2] : (R)0);
+    face_eval<2, R>(lo, nb, Wm, wp, kend - 1, nk, true, Ph, hz);
+    finish_node<R>(A, i, j, kend - 1, part, hz, hz_lo);
   }
 }
 

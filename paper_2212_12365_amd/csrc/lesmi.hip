@@ -546,7 +546,7 @@ int les_init_grid(const les_params* params, const double* xyz, les_ctx** out) {
   c->dims = D;
   c->phys = make_phys(*params);
   // Stage kernel launch shape: the fastest measured on the 256 x 128 x 128 jet.
-  c->tile = params->precision == LES_MIXED ? 0 : 5;
+  c->tile = params->precision == LES_MIXED ? 0 : 3;
   c->n_updated = 1;
   for (int d = 0; d < 3; ++d) c->n_updated *= D.per[d] ? D.n[d] : D.n[d] - 2;
   hipGetDevice(&c->device);
