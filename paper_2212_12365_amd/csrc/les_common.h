@@ -61,7 +61,7 @@ struct les_ctx {
   double* qb = nullptr;
 
   // Node records of the stage kernels [kRecCount][N] (FP64 form), or the mixed form's
-  // FP32 records and FP32 copy of the metrics.
+  // FP32 records [kRecCount][N] and FP32 copy of the metrics.
   double* rec = nullptr;
   float* rec32 = nullptr;
   float* S32 = nullptr;

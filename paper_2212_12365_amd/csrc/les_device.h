@@ -41,6 +41,17 @@ struct PhysT {
   }
 };
 
+// a * b + c with one rounding. The flux formulas spell out their fused products with it
+// (the translation units are compiled without automatic contraction), so every evaluation
+// context of a face rounds the same way.
+template <typename R>
+__device__ __forceinline__ R fmadd(R a, R b, R c) {
+  if constexpr (sizeof(R) == sizeof(float))
+    return __builtin_fmaf(a, b, c);
+  else
+    return __builtin_fma(a, b, c);
+}
+
 // Primitive variables of a node (paper, LES formulation: equation of state and System-I
 // energy, in reference units): p = (gamma-1)(e - rho|u|^2/2), T = gamma p / rho, a^2 = T.
 struct Prim {
@@ -132,7 +143,7 @@ __device__ __forceinline__ void dissipation(R lf, R nuA, R nuB, const R* dW, con
   R eps4 = (R)P.k4 - eps2;
   eps4 = eps4 > (R)0 ? eps4 : (R)0;
 #pragma unroll
-  for (int c = 0; c < 5; ++c) D[c] = lf * (eps2 * dW[c] - eps4 * d3W[c]);
+  for (int c = 0; c < 5; ++c) D[c] = lf * fmadd(eps2, dW[c], -(eps4 * d3W[c]));
 }
 
 // Viscous + SGS face flux (paper, Transformation of Coordinates: viscous flux vectors;
@@ -149,24 +160,26 @@ __device__ __forceinline__ void viscous_flux(const R* Sf, R jinvf, const R gxi[4
   for (int v = 0; v < 4; ++v)
 #pragma unroll
     for (int n = 0; n < 3; ++n)
-      g[v][n] = Jf * (Sf[n] * gxi[v][0] + Sf[3 + n] * gxi[v][1] + Sf[6 + n] * gxi[v][2]);
-  R visc = muf * (R)P.inv_re + mutf;
-  R kappa = (muf * (R)P.inv_re * (R)P.inv_pr + mutf * (R)P.inv_prs) * (R)P.inv_gm1;
+      g[v][n] = Jf * fmadd(Sf[6 + n], gxi[v][2], fmadd(Sf[3 + n], gxi[v][1], Sf[n] * gxi[v][0]));
+  const R mi = muf * (R)P.inv_re;
+  R visc = mi + mutf;
+  R kappa = fmadd(mi, (R)P.inv_pr, mutf * (R)P.inv_prs) * (R)P.inv_gm1;
   R div = g[0][0] + g[1][1] + g[2][2];
-  R t00 = visc * ((R)2 * g[0][0] - ((R)2 / (R)3) * div);
-  R t11 = visc * ((R)2 * g[1][1] - ((R)2 / (R)3) * div);
-  R t22 = visc * ((R)2 * g[2][2] - ((R)2 / (R)3) * div);
+  const R c23 = -((R)2 / (R)3);
+  R t00 = visc * fmadd(c23, div, (R)2 * g[0][0]);
+  R t11 = visc * fmadd(c23, div, (R)2 * g[1][1]);
+  R t22 = visc * fmadd(c23, div, (R)2 * g[2][2]);
   R t01 = visc * (g[0][1] + g[1][0]);
   R t02 = visc * (g[0][2] + g[2][0]);
   R t12 = visc * (g[1][2] + g[2][1]);
-  R bx = t00 * ub[0] + t01 * ub[1] + t02 * ub[2] + kappa * g[3][0];
-  R by = t01 * ub[0] + t11 * ub[1] + t12 * ub[2] + kappa * g[3][1];
-  R bz = t02 * ub[0] + t12 * ub[1] + t22 * ub[2] + kappa * g[3][2];
+  R bx = fmadd(kappa, g[3][0], fmadd(t02, ub[2], fmadd(t01, ub[1], t00 * ub[0])));
+  R by = fmadd(kappa, g[3][1], fmadd(t12, ub[2], fmadd(t11, ub[1], t01 * ub[0])));
+  R bz = fmadd(kappa, g[3][2], fmadd(t22, ub[2], fmadd(t12, ub[1], t02 * ub[0])));
   const R* sd = Sf + 3 * d;
-  F[1] = sd[0] * t00 + sd[1] * t01 + sd[2] * t02;
-  F[2] = sd[0] * t01 + sd[1] * t11 + sd[2] * t12;
-  F[3] = sd[0] * t02 + sd[1] * t12 + sd[2] * t22;
-  F[4] = sd[0] * bx + sd[1] * by + sd[2] * bz;
+  F[1] = fmadd(sd[2], t02, fmadd(sd[1], t01, sd[0] * t00));
+  F[2] = fmadd(sd[2], t12, fmadd(sd[1], t11, sd[0] * t01));
+  F[3] = fmadd(sd[2], t22, fmadd(sd[1], t12, sd[0] * t02));
+  F[4] = fmadd(sd[2], bz, fmadd(sd[1], by, sd[0] * bx));
 }
 
 }  // namespace lesmi

@@ -7,12 +7,16 @@
 
 namespace lesmi {
 
-// Node record fields, each a plane of N doubles.
+// Node record fields, each a plane of N values (FP64, or FP32 in the mixed form). The
+// primitive variables and the molecular viscosity are not stored: the face kernel forms them
+// from the state it stages.
 enum {
-  kRecU = 0, kRecV, kRecW, kRecT, kRecP, kRecMu, kRecMut,
-  kRecLb,           // three planes: scaled spectral radius along xi, eta, zeta
+  kRecMut = 0,
+  kRecLb,               // three planes: scaled spectral radius along xi, eta, zeta
   kRecNu = kRecLb + 3,  // three planes: pressure sensor along xi, eta, zeta
-  kRecCount = kRecNu + 3
+  kRecDz = kRecNu + 3,  // four planes: centred zeta differences (x_{k+1} - x_{k-1})/2 of
+                        // u, v, w, T
+  kRecCount = kRecDz + 4
 };
 
 struct StageArgs {

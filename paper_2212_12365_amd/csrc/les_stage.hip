@@ -54,16 +54,37 @@ __device__ __forceinline__ double* records_of<double>(const StageArgs& A) { retu
 template <>
 __device__ __forceinline__ float* records_of<float>(const StageArgs& A) { return A.rec32; }
 
-// Component c of the dissipated vector W = Q + (0, 0, 0, 0, p) at node offset o, less the
-// reference W_ref of the mixed form (the subtraction is in FP64; W_ref is 0 in FP64). prel
-// is the node record's p - p_ref.
+// Face inputs formed from the state at one node: the dissipated vector W (less W_ref), p -
+// p_ref, u, v, w, T and the molecular viscosity, each rounded to R from the FP64 primitive
+// variables (the node kernel works from the same FP64 values).
 template <typename R>
-__device__ __forceinline__ R w_of(const StageArgs& A, unsigned o, int c, R prel) {
+struct NodeState {
+  R W[5], prel, f[4], mu;
+};
+
+template <typename R>
+__device__ __forceinline__ NodeState<R> node_state(const StageArgs& A, unsigned o) {
   const int N = (int)A.D.N;
-  double w = A.q[c * N + o];
-  if (c == 4) w += (double)prel + A.P.p_ref;
-  if constexpr (sizeof(R) == sizeof(float)) w -= A.P.wref[c];
-  return (R)w;
+  const double* __restrict__ q = A.q;
+  const double q0 = q[o], q1 = q[N + o], q2 = q[2 * N + o], q3 = q[3 * N + o],
+               q4 = q[4 * N + o];
+  const Prim s = prim_from_q(q0, q1, q2, q3, q4, A.P);
+  NodeState<R> n;
+  n.prel = (R)(s.p - A.P.p_ref);
+  const double qc[5] = {q0, q1, q2, q3, q4};
+#pragma unroll
+  for (int c = 0; c < 5; ++c) {
+    double w = qc[c];
+    if (c == 4) w += (double)n.prel + A.P.p_ref;
+    if constexpr (sizeof(R) == sizeof(float)) w -= A.P.wref[c];
+    n.W[c] = (R)w;
+  }
+  n.f[0] = (R)s.u;
+  n.f[1] = (R)s.v;
+  n.f[2] = (R)s.w;
+  n.f[3] = (R)s.T;
+  n.mu = sutherland<R>(n.f[3], PhysT<R>(A.P));
+  return n;
 }
 
 // Node record of one node. Primitive variables are formed in FP64 from the FP64 state;
@@ -87,6 +108,7 @@ __device__ __forceinline__ void node_record(const StageArgs& A, int i, int j, in
   // direction) and pressure sensors along e.
   R du[3][3];
   R nu[3];
+  R dzT = (R)0;  // centred zeta difference of T (zeta is periodic)
   for (int e = 0; e < 3; ++e) {
     int n = D.n[e], m = ix[e];
     int stride = e == 0 ? 1 : (e == 1 ? D.n[0] : D.n[0] * D.n[1]);
@@ -95,6 +117,7 @@ __device__ __forceinline__ void node_record(const StageArgs& A, int i, int j, in
       du[e][0] = (R)0.5 * ((R)zp.u - (R)zm.u);
       du[e][1] = (R)0.5 * ((R)zp.v - (R)zm.v);
       du[e][2] = (R)0.5 * ((R)zp.w - (R)zm.w);
+      dzT = (R)0.5 * ((R)zp.T - (R)zm.T);
       nu[e] = sensor<R>((R)zm.p, sp, (R)zp.p);
     } else if (interior) {
       int mp = m + 1 == n ? 0 : m + 1, mm = m == 0 ? n - 1 : m - 1;
@@ -103,6 +126,7 @@ __device__ __forceinline__ void node_record(const StageArgs& A, int i, int j, in
       du[e][0] = (R)0.5 * ((R)a.u - (R)b.u);
       du[e][1] = (R)0.5 * ((R)a.v - (R)b.v);
       du[e][2] = (R)0.5 * ((R)a.w - (R)b.w);
+      if (e == 2) dzT = (R)0.5 * ((R)a.T - (R)b.T);
       nu[e] = sensor<R>((R)b.p, sp, (R)a.p);
     } else {
       int sg = m == 0 ? 1 : -1;  // towards the interior
@@ -129,12 +153,6 @@ __device__ __forceinline__ void node_record(const StageArgs& A, int i, int j, in
   R lb[3];
   scaled_radii<R>(l0, l1, l2, lb);
   R* __restrict__ r = records_of<R>(A);
-  r[kRecU * N + o] = su;
-  r[kRecV * N + o] = sv;
-  r[kRecW * N + o] = sw;
-  r[kRecT * N + o] = T;
-  r[kRecP * N + o] = (R)(s.p - A.P.p_ref);
-  r[kRecMu * N + o] = sutherland<R>(T, P);
   r[kRecMut * N + o] = mut;
   r[(kRecLb + 0) * N + o] = lb[0];
   r[(kRecLb + 1) * N + o] = lb[1];
@@ -142,6 +160,10 @@ __device__ __forceinline__ void node_record(const StageArgs& A, int i, int j, in
   r[(kRecNu + 0) * N + o] = nu[0];
   r[(kRecNu + 1) * N + o] = nu[1];
   r[(kRecNu + 2) * N + o] = nu[2];
+  r[(kRecDz + 0) * N + o] = du[2][0];
+  r[(kRecDz + 1) * N + o] = du[2][1];
+  r[(kRecDz + 2) * N + o] = du[2][2];
+  r[(kRecDz + 3) * N + o] = dzT;
   if (A.mut_out) A.mut_out[o] = (double)mut;
   if (A.feat || A.fscale || A.fsmag) {  // inputs of the learned closure
     R g[3][3], f[kMlpIn];
@@ -181,7 +203,11 @@ __global__ void __launch_bounds__(256) k_nodes_march(StageArgs A, int kchunk) {
   Prim z0 = load_prim(A.q, N, o0 + pl * kbeg, A.P);
   for (int k = kbeg; k < kend; ++k) {
     const Prim zp = load_prim(A.q, N, o0 + pl * (k + 1 == nk ? 0 : k + 1), A.P);
-    node_record<R, true>(A, i, j, k, zm, z0, zp);
+    // (i, j) pass through an empty asm statement so that the neighbour addresses are formed
+    // on each plane rather than hoisted out of the loop into registers.
+    int il = i, jl = j;
+    if constexpr (sizeof(R) == sizeof(float)) asm volatile("" : "+v"(il), "+v"(jl));
+    node_record<R, true>(A, il, jl, k, zm, z0, zp);
     zm = z0;
     z0 = zp;
   }
@@ -277,6 +303,7 @@ struct GlobalNodeZ {
   int N;
   const R* __restrict__ rec;
   const R* __restrict__ Sm;
+  NodeState<R> n;
   __device__ GlobalNodeZ(const StageArgs& A_, int i, int j, int k)
       : A(A_), N((int)A_.D.N), rec(records_of<R>(A_)), Sm(metrics_of<R>(A_)) {
     const int ni = A.D.n[0], nj = A.D.n[1];
@@ -285,19 +312,21 @@ struct GlobalNodeZ {
     im = i == 0 ? o + (unsigned)(ni - 1) : o - 1;
     jp = j + 1 == nj ? o - (unsigned)((nj - 1) * ni) : o + ni;
     jm = j == 0 ? o + (unsigned)((nj - 1) * ni) : o - ni;
+    n = node_state<R>(A, o);
   }
-  __device__ R p() const { return rec[kRecP * N + o]; }
-  __device__ R W(int c) const { return w_of<R>(A, o, c, c == 4 ? p() : (R)0); }
-  __device__ R f(int v) const { return rec[(kRecU + v) * N + o]; }
-  __device__ R mu() const { return rec[kRecMu * N + o]; }
+  __device__ R p() const { return n.prel; }
+  __device__ R W(int c) const { return n.W[c]; }
+  __device__ R f(int v) const { return n.f[v]; }
+  __device__ R mu() const { return n.mu; }
   __device__ R mut() const { return rec[kRecMut * N + o]; }
   __device__ R S(int c) const { return Sm[c * N + o]; }
   __device__ R jinv() const { return (R)A.jinv[o]; }
   __device__ R lb() const { return rec[(kRecLb + 2) * N + o]; }
   __device__ R nu() const { return rec[(kRecNu + 2) * N + o]; }
   __device__ R dt(int e, int v) const {
-    if (e == 0) return (R)0.5 * (rec[(kRecU + v) * N + ip] - rec[(kRecU + v) * N + im]);
-    return (R)0.5 * (rec[(kRecU + v) * N + jp] - rec[(kRecU + v) * N + jm]);
+    const NodeState<R> a = node_state<R>(A, e == 0 ? ip : jp);
+    const NodeState<R> b = node_state<R>(A, e == 0 ? im : jm);
+    return (R)0.5 * (a.f[v] - b.f[v]);
   }
 };
 
@@ -484,7 +513,6 @@ __device__ __forceinline__ void stage_block(const StageArgs& A, int bx, int by, 
   const double* __restrict__ q = A.q;
   const R* __restrict__ rec = records_of<R>(A);
   const R* __restrict__ S = metrics_of<R>(A);
-  const unsigned pl = (unsigned)(ni * nj);
 
   // State of the column between planes: the zeta face below the pending node (hz_lo), the
   // pending node's xi/eta flux sum (part) and face inputs (lo), and W one plane below it.
@@ -499,13 +527,8 @@ __device__ __forceinline__ void stage_block(const StageArgs& A, int bx, int by, 
     const int kp = kbeg + 1 == nk ? 0 : kbeg + 1;
     const unsigned om = (unsigned)(i + ni * (j + nj * kl2));
     const unsigned op = (unsigned)(i + ni * (j + nj * kp));
-    R wm[5], wp[5];
-#pragma unroll
-    for (int c = 0; c < 5; ++c) {
-      wm[c] = w_of<R>(A, om, c, c == 4 ? rec[kRecP * N + om] : (R)0);
-      wp[c] = w_of<R>(A, op, c, c == 4 ? rec[kRecP * N + op] : (R)0);
-    }
-    face_eval<2, R>(na, nb, wm, wp, kl, nk, true, Ph, hz_lo);
+    const NodeState<R> sm = node_state<R>(A, om), sp = node_state<R>(A, op);
+    face_eval<2, R>(na, nb, sm.W, sp.W, kl, nk, true, Ph, hz_lo);
 #pragma unroll
     for (int c = 0; c < 5; ++c) Wm[c] = na.W(c);
   }
@@ -516,20 +539,24 @@ __device__ __forceinline__ void stage_block(const StageArgs& A, int bx, int by, 
     // from it are then formed anew on each plane instead of being hoisted out of the loop
     // (where they would hold registers across the face arithmetic).
     int tl = tid;
-    asm volatile("" : "+v"(tl));
+    if constexpr (sizeof(R) == sizeof(double)) asm volatile("" : "+v"(tl));
     // Staging loads of slot s of the two-node ring (W and p) and of the one-node ring (the
     // other face inputs); nodes outside a non-periodic range stage zeros.
-    auto load_w = [&](int s, R(&v)[6]) {
+    // A slot of the two-node ring inside the one-node ring also supplies that ring's u, v,
+    // w, T and molecular viscosity (v[6..10]).
+    auto load_w = [&](int s, R(&v)[11]) {
       const int ia = wrap_or_out(i0 - 2 + s % PL::RX2, ni, D.per[0]);
       const int ja = wrap_or_out(j0 - 2 + s / PL::RX2, nj, D.per[1]);
 #pragma unroll
-      for (int c = 0; c < 6; ++c) v[c] = (R)0;
+      for (int c = 0; c < 11; ++c) v[c] = (R)0;
       if (s < PL::NW && ia >= 0 && ja >= 0) {
-        const unsigned o = (unsigned)(ia + ni * (ja + nj * k));
-        const R pr = rec[kRecP * N + o];
+        const NodeState<R> n = node_state<R>(A, (unsigned)(ia + ni * (ja + nj * k)));
 #pragma unroll
-        for (int c = 0; c < 5; ++c) v[c] = w_of<R>(A, o, c, pr);
-        v[5] = pr;
+        for (int c = 0; c < 5; ++c) v[c] = n.W[c];
+        v[5] = n.prel;
+#pragma unroll
+        for (int c = 0; c < 4; ++c) v[6 + c] = n.f[c];
+        v[10] = n.mu;
       }
     };
     auto load_f = [&](int s, R(&v)[sNF]) {
@@ -539,20 +566,12 @@ __device__ __forceinline__ void stage_block(const StageArgs& A, int bx, int by, 
       for (int c = 0; c < sNF; ++c) v[c] = (R)0;
       if (s < PL::N1 && ia >= 0 && ja >= 0) {
         const unsigned o = (unsigned)(ia + ni * (ja + nj * k));
-        v[sU] = rec[kRecU * N + o];
-        v[sV] = rec[kRecV * N + o];
-        v[sWv] = rec[kRecW * N + o];
-        v[sT] = rec[kRecT * N + o];
-        v[sMu] = rec[kRecMu * N + o];
         v[sMut] = rec[kRecMut * N + o];
 #pragma unroll
         for (int c = 0; c < 9; ++c) v[sS0 + c] = S[c * N + o];
         v[sJinv] = (R)A.jinv[o];
-        const unsigned op = k + 1 == nk ? o - (unsigned)(nk - 1) * pl : o + pl;
-        const unsigned om = k == 0 ? o + (unsigned)(nk - 1) * pl : o - pl;
 #pragma unroll
-        for (int c = 0; c < 4; ++c)
-          v[sDz + c] = (R)0.5 * (rec[(kRecU + c) * N + op] - rec[(kRecU + c) * N + om]);
+        for (int c = 0; c < 4; ++c) v[sDz + c] = rec[(kRecDz + c) * N + o];
       }
     };
     // The plane is staged in two groups of loads, each written to LDS as it arrives.
@@ -561,7 +580,7 @@ __device__ __forceinline__ void stage_block(const StageArgs& A, int bx, int by, 
     // pending zeta face).
     R zl[2] = {0, 0}, wp[5] = {0, 0, 0, 0, 0};
     {
-      R vw[MW][6], vf[sNF];
+      R vw[MW][11], vf[sNF];
 #pragma unroll
       for (int r = 0; r < MW; ++r) load_w(tl + r * NT, vw[r]);
       load_f(tl, vf);
@@ -574,8 +593,7 @@ __device__ __forceinline__ void stage_block(const StageArgs& A, int bx, int by, 
         const int kp = k + 1 == nk ? 0 : k + 1;
         const unsigned o2 = (unsigned)(i + ni * (j + nj * kp));
 #pragma unroll
-        for (int c = 0; c < 5; ++c)
-          wp[c] = w_of<R>(A, o2, c, c == 4 ? rec[kRecP * N + o2] : (R)0);
+        for (int c = 0; c < 5; ++c) wp[c] = node_state<R>(A, o2).W[c];
       }
 #pragma unroll
       for (int r = 0; r < MW; ++r) {
@@ -583,10 +601,14 @@ __device__ __forceinline__ void stage_block(const StageArgs& A, int bx, int by, 
         if (s < PL::NW)
 #pragma unroll
           for (int c = 0; c < 6; ++c) L.in.W[c][s] = vw[r][c];
+        const int x1 = s % PL::RX2 - 1, y1 = s / PL::RX2 - 1;  // one-node ring position
+        if (s < PL::NW && x1 >= 0 && x1 < PL::RX1 && y1 >= 0 && y1 < PL::RY1)
+#pragma unroll
+          for (int c = 0; c < 5; ++c) L.in.F[sU + c][x1 + PL::RX1 * y1] = vw[r][6 + c];
       }
       if (tl < PL::N1)
 #pragma unroll
-        for (int c = 0; c < sNF; ++c) L.in.F[c][tl] = vf[c];
+        for (int c = sMut; c < sNF; ++c) L.in.F[c][tl] = vf[c];
     }
     // Group 2: the other slots of the one-node ring, and the scaled spectral radius and
     // sensor of the xi- and eta-face nodes.
@@ -624,7 +646,7 @@ __device__ __forceinline__ void stage_block(const StageArgs& A, int bx, int by, 
         const int s = tl + r * NT;
         if (s < PL::N1)
 #pragma unroll
-          for (int c = 0; c < sNF; ++c) L.in.F[c][s] = vf[r - 1][c];
+          for (int c = sMut; c < sNF; ++c) L.in.F[c][s] = vf[r - 1][c];
       }
 #pragma unroll
       for (int r = 0; r < MDX; ++r) {
@@ -647,7 +669,7 @@ __device__ __forceinline__ void stage_block(const StageArgs& A, int bx, int by, 
 
     // Zeta face between planes k-1 and k, and the update of the node on plane k-1.
     int tf = tid;  // laundered again for the face phase
-    asm volatile("" : "+v"(tf));
+    if constexpr (sizeof(R) == sizeof(double)) asm volatile("" : "+v"(tf));
     const int own1 = tf % TX + 1 + PL::RX1 * (tf / TX + 1);
     const int own2 = tf % TX + 2 + PL::RX2 * (tf / TX + 2);
     if (pending) {
@@ -751,7 +773,7 @@ __device__ __forceinline__ void stage_block(const StageArgs& A, int bx, int by, 
     const unsigned o2 = (unsigned)(i + ni * (j + nj * kt2));
     R wp[5], hz[5];
 #pragma unroll
-    for (int c = 0; c < 5; ++c) wp[c] = w_of<R>(A, o2, c, c == 4 ? rec[kRecP * N + o2] : (R)0);
+    for (int c = 0; c < 5; ++c) wp[c] = node_state<R>(A, o2).W[c];
     face_eval<2, R>(lo, nb, Wm, wp, kend - 1, nk, true, Ph, hz);
     finish_node<R>(A, i, j, kend - 1, part, hz, hz_lo);
   }
