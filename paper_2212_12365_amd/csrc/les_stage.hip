@@ -92,9 +92,14 @@ __device__ __forceinline__ NodeState<R> node_state(const StageArgs& A, unsigned 
 // Node record of node (i, j, k). With kQueue the primitive variables of the node and of its
 // zeta neighbours (periodic zeta) are given by the caller (zm, z0, zp); otherwise they are
 // loaded here.
+// With nl non-null, the centred xi and eta neighbours' u, v, w, p come from a plane tile in
+// LDS: nl[f * kNodeTileN + npos +- 1] along xi and +- kNodeTileX along eta (f = u, v, w, p).
+constexpr int kNodeTileX = 66, kNodeTileY = 6, kNodeTileN = kNodeTileX * kNodeTileY;
+
 template <typename R, bool kQueue>
 __device__ __forceinline__ void node_record(const StageArgs& A, int i, int j, int k,
-                                            const Prim& zm, const Prim& z0, const Prim& zp) {
+                                            const Prim& zm, const Prim& z0, const Prim& zp,
+                                            const R* nl = nullptr, int npos = 0) {
   const Dims& D = A.D;
   const PhysT<R> P(A.P);
   const int N = (int)D.N;
@@ -119,6 +124,14 @@ __device__ __forceinline__ void node_record(const StageArgs& A, int i, int j, in
       du[e][2] = (R)0.5 * ((R)zp.w - (R)zm.w);
       dzT = (R)0.5 * ((R)zp.T - (R)zm.T);
       nu[e] = sensor<R>((R)zm.p, sp, (R)zp.p);
+    } else if (interior && nl && e < 2) {
+      const int st = e == 0 ? 1 : kNodeTileX;
+      const R* a = nl + npos + st;
+      const R* b = nl + npos - st;
+      du[e][0] = (R)0.5 * (a[0] - b[0]);
+      du[e][1] = (R)0.5 * (a[kNodeTileN] - b[kNodeTileN]);
+      du[e][2] = (R)0.5 * (a[2 * kNodeTileN] - b[2 * kNodeTileN]);
+      nu[e] = sensor<R>(b[3 * kNodeTileN], sp, a[3 * kNodeTileN]);
     } else if (interior) {
       int mp = m + 1 == n ? 0 : m + 1, mm = m == 0 ? n - 1 : m - 1;
       Prim a = load_prim(q, N, o + (mp - m) * stride, A.P);
@@ -208,6 +221,85 @@ __global__ void __launch_bounds__(256) k_nodes_march(StageArgs A, int kchunk) {
     int il = i, jl = j;
     if constexpr (sizeof(R) == sizeof(float)) asm volatile("" : "+v"(il), "+v"(jl));
     node_record<R, true>(A, il, jl, k, zm, z0, zp);
+    zm = z0;
+    z0 = zp;
+  }
+}
+
+// The same march with the in-plane neighbours shared through LDS: each thread forms the
+// primitive variables of its own node once per plane (the queue's upper plane) and threads
+// 0..135 those of the tile's one-node ring; the centred xi and eta differences then read
+// the tile. One-sided differences at the ends of a non-periodic direction read global
+// memory as before.
+template <typename R>
+__global__ void __launch_bounds__(256) k_nodes_tile(StageArgs A, int kchunk) {
+  __shared__ R Lp[4 * kNodeTileN];
+  const Dims& D = A.D;
+  const int ni = D.n[0], nj = D.n[1], nk = D.n[2], N = (int)D.N;
+  const int tx = threadIdx.x, ty = threadIdx.y, tid = tx + 64 * ty;
+  const int i0 = blockIdx.x * 64, j0 = blockIdx.y * 4;
+  const int i = i0 + tx, j = j0 + ty;
+  const bool mine = i < ni && j < nj;
+  const int kbeg = blockIdx.z * kchunk, kend = min(kbeg + kchunk, nk);
+  const int pl = ni * nj;
+  // Ring slot of this thread (threads 0..135): rows j0 - 1 and j0 + 4, then columns i0 - 1
+  // and i0 + 64. A thread whose own node lies past the end of a periodic direction stages
+  // the wrapped node in its own slot instead (ragged tiles).
+  int hpos = -1, ho = -1;
+  if (tid < 136) {
+    int hx, hy;
+    if (tid < 64) { hx = tid + 1; hy = 0; }
+    else if (tid < 128) { hx = tid - 63; hy = kNodeTileY - 1; }
+    else if (tid < 132) { hx = 0; hy = tid - 127; }
+    else { hx = kNodeTileX - 1; hy = tid - 131; }
+    const int ia = wrap_or_out(i0 - 1 + hx, ni, D.per[0]);
+    const int ja = wrap_or_out(j0 - 1 + hy, nj, D.per[1]);
+    if (ia >= 0 && ja >= 0) {
+      hpos = hx + kNodeTileX * hy;
+      ho = ia + ni * ja;
+    }
+  }
+  const int own = (tx + 1) + kNodeTileX * (ty + 1);
+  int wo = -1;  // wrapped node staged in the own slot by a thread outside the grid
+  if (!mine) {
+    const bool oki = i < ni || D.per[0], okj = j < nj || D.per[1];
+    if (oki && okj) wo = (i % ni) + ni * (j % nj);
+  }
+  const int o0 = i + ni * j;
+  Prim zm{}, z0{};
+  if (mine) {
+    zm = load_prim(A.q, N, o0 + pl * (kbeg == 0 ? nk - 1 : kbeg - 1), A.P);
+    z0 = load_prim(A.q, N, o0 + pl * kbeg, A.P);
+  }
+  for (int k = kbeg; k < kend; ++k) {
+    Prim zp{}, h{}, w{};
+    if (mine) zp = load_prim(A.q, N, o0 + pl * (k + 1 == nk ? 0 : k + 1), A.P);
+    if (ho >= 0) h = load_prim(A.q, N, ho + pl * k, A.P);
+    if (wo >= 0) w = load_prim(A.q, N, wo + pl * k, A.P);
+    __syncthreads();  // the previous plane's tile has been read
+    if (mine) {
+      Lp[own] = (R)z0.u;
+      Lp[kNodeTileN + own] = (R)z0.v;
+      Lp[2 * kNodeTileN + own] = (R)z0.w;
+      Lp[3 * kNodeTileN + own] = (R)z0.p;
+    } else if (wo >= 0) {
+      Lp[own] = (R)w.u;
+      Lp[kNodeTileN + own] = (R)w.v;
+      Lp[2 * kNodeTileN + own] = (R)w.w;
+      Lp[3 * kNodeTileN + own] = (R)w.p;
+    }
+    if (ho >= 0) {
+      Lp[hpos] = (R)h.u;
+      Lp[kNodeTileN + hpos] = (R)h.v;
+      Lp[2 * kNodeTileN + hpos] = (R)h.w;
+      Lp[3 * kNodeTileN + hpos] = (R)h.p;
+    }
+    __syncthreads();
+    // Indices pass through an empty asm statement: their derived addresses are formed on
+    // each plane instead of holding registers across the loop.
+    int il = i, jl = j, ol = own;
+    asm volatile("" : "+v"(il), "+v"(jl), "+v"(ol));
+    if (mine) node_record<R, true>(A, il, jl, k, zm, z0, zp, Lp, ol);
     zm = z0;
     z0 = zp;
   }
@@ -815,9 +907,9 @@ hipError_t launch_nodes(const StageArgs& A, hipStream_t s) {
     const int kchunk = (A.D.n[2] + nz - 1) / nz;
     const dim3 grid(gx, gy, (A.D.n[2] + kchunk - 1) / kchunk);
     if (A.mixed)
-      hipLaunchKernelGGL(k_nodes_march<float>, grid, block, 0, s, A, kchunk);
+      hipLaunchKernelGGL(k_nodes_tile<float>, grid, block, 0, s, A, kchunk);
     else
-      hipLaunchKernelGGL(k_nodes_march<double>, grid, block, 0, s, A, kchunk);
+      hipLaunchKernelGGL(k_nodes_tile<double>, grid, block, 0, s, A, kchunk);
     return hipGetLastError();
   }
   dim3 grid(gx, gy, A.D.n[2]);
