@@ -99,7 +99,7 @@ __global__ void __launch_bounds__(256) k_batch_bc(const StageArgs* __restrict__ 
   }
 }
 
-// State check of each member's state; items are the node items (member, bx, by, k).
+// State check of each member's state; items are (member, bx, by, k) over 64 x 4 blocks.
 __global__ void __launch_bounds__(256) k_batch_check(const StageArgs* __restrict__ row0,
                                                      const MemberArgs* __restrict__ M,
                                                      const int4* __restrict__ work, int nwork) {
@@ -135,9 +135,11 @@ struct les_batch {
 
   StageArgs* d_args = nullptr;  // [kRows][n]
   MemberArgs* d_mem = nullptr;  // [n]
-  int4 *d_wnodes = nullptr, *d_wfaces = nullptr, *d_waxis = nullptr, *d_wbc = nullptr,
-       *d_wdt = nullptr;
-  int nwnodes = 0, nwfaces = 0, nwaxis = 0, nwbc = 0, nwdt = 0;
+  // Work lists: node kernel (tile, z-chunk), checks (64 x 4 block, plane), face kernel,
+  // axis means, boundary nodes, time-step partials.
+  int4 *d_wnodes = nullptr, *d_wcheck = nullptr, *d_wfaces = nullptr, *d_waxis = nullptr,
+       *d_wbc = nullptr, *d_wdt = nullptr;
+  int nwnodes = 0, nwcheck = 0, nwfaces = 0, nwaxis = 0, nwbc = 0, nwdt = 0;
   double* d_dts = nullptr;
   int* d_flags = nullptr;
 
@@ -208,7 +210,7 @@ int build_face_work(les_batch* b) {
 }
 
 int build_static_work(les_batch* b) {
-  std::vector<int4> wn, wa, wb, wd;
+  std::vector<int4> wn, wc, wa, wb, wd;
   std::vector<MemberArgs> mem;
   for (int mi = 0; mi < (int)b->m.size(); ++mi) {
     les_ctx* c = b->m[mi];
@@ -218,9 +220,14 @@ int build_static_work(les_batch* b) {
     for (int k = 0; k < D.n[2]; ++k)
       for (int by = 0; by < gy; ++by)
         for (int bx = 0; bx < gx; ++bx) {
-          wn.push_back(make_int4(mi, bx, by, k));
+          wc.push_back(make_int4(mi, bx, by, k));
           wd.push_back(make_int4(mi, bx | (by << 16), k, slot++));
         }
+    const int kc = nodes_kchunk(D);
+    for (int k0 = 0; k0 < D.n[2]; k0 += kc)
+      for (int by = 0; by < gy; ++by)
+        for (int bx = 0; bx < gx; ++bx)
+          wn.push_back(make_int4(mi, bx | (by << 16), k0, std::min(k0 + kc, D.n[2])));
     if (D.jet) {
       for (int i = 1; i <= D.n[0] - 2; ++i) wa.push_back(make_int4(mi, i, 0, 0));
       long long nbc = 2LL * (D.n[0] - 2) * D.n[2] + 2LL * D.n[1] * D.n[2];
@@ -239,11 +246,13 @@ int build_static_work(les_batch* b) {
     mem.push_back(M);
   }
   b->nwnodes = (int)wn.size();
+  b->nwcheck = (int)wc.size();
   b->occ_nodes = occupancy_of(b, false);
   b->nwaxis = (int)wa.size();
   b->nwbc = (int)wb.size();
   b->nwdt = (int)wd.size();
   BHIP(b, upload(&b->d_wnodes, wn));
+  BHIP(b, upload(&b->d_wcheck, wc));
   BHIP(b, upload(&b->d_waxis, wa));
   BHIP(b, upload(&b->d_wbc, wb));
   BHIP(b, upload(&b->d_wdt, wd));
@@ -454,8 +463,8 @@ int les_batch_step(les_batch* b, double* const* q, int nsteps, double cfl, doubl
     }
   }
   const StageArgs* row0 = b->d_args;
-  hipLaunchKernelGGL(k_batch_check, dim3(persistent_grid(b, 4, b->nwnodes)), dim3(64, 4), 0, s,
-                     row0, b->d_mem, b->d_wnodes, b->nwnodes);
+  hipLaunchKernelGGL(k_batch_check, dim3(persistent_grid(b, 4, b->nwcheck)), dim3(64, 4), 0, s,
+                     row0, b->d_mem, b->d_wcheck, b->nwcheck);
   hipLaunchKernelGGL(k_batch_gather, dim3((n + 63) / 64), dim3(64), 0, s, b->d_mem, n, b->d_dts,
                      b->d_flags);
   rc = check_launch(b, "batch check");
@@ -533,8 +542,8 @@ void les_batch_destroy(les_batch* b) {
   (void)hipDeviceSynchronize();
   drop_graph(b);
   if (b->cap) (void)hipStreamDestroy(b->cap);
-  void* ptrs[] = {b->d_args, b->d_mem,   b->d_wnodes, b->d_wfaces, b->d_waxis,
-                  b->d_wbc,  b->d_wdt,   b->d_dts,    b->d_flags};
+  void* ptrs[] = {b->d_args, b->d_mem, b->d_wnodes, b->d_wcheck, b->d_wfaces,
+                  b->d_waxis, b->d_wbc, b->d_wdt,    b->d_dts,    b->d_flags};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
   delete b;

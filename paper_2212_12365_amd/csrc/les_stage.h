@@ -69,7 +69,10 @@ struct BatchLaunch {
   bool mixed;
   int* occupancy;
 };
+// Node-kernel items are (member, bx | by << 16, kbeg, kend) over 64 x 4 column tiles and
+// z-chunks of nodes_kchunk planes.
 hipError_t launch_nodes_batch(const BatchLaunch& B, hipStream_t s);
+int nodes_kchunk(const Dims& D);
 
 // Stage arguments of a context for input state q (lesmi.hip).
 StageArgs stage_args_of(les_ctx* c, const double* q);

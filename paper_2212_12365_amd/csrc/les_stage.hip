@@ -191,56 +191,22 @@ __device__ __forceinline__ void node_record(const StageArgs& A, int i, int j, in
   }
 }
 
-// One 64 x 4 block of nodes at (bx, by) in plane k.
+// Node records of the 64 x 4 column tile (bx, by) over the z-planes kbeg .. kend-1 (zeta
+// periodic), one thread per (i, j) column in 64 x 4 blocks. The primitive variables of
+// planes k-1, k, k+1 of the own column stay in registers; per plane, each thread stages its
+// node's u, v, w, p in the LDS tile Lp and threads 0..135 those of the tile's one-node ring,
+// so the centred xi and eta differences read the tile and each node's primitive variables
+// are formed about 1.5 times per plane. One-sided differences at the ends of a non-periodic
+// direction read global memory.
 template <typename R>
-__device__ __forceinline__ void nodes_block(const StageArgs& A, int bx, int by, int k) {
-  const int i = bx * 64 + threadIdx.x, j = by * 4 + threadIdx.y;
-  if (i >= A.D.n[0] || j >= A.D.n[1]) return;
-  const Prim none{};
-  node_record<R, false>(A, i, j, k, none, none, none);
-}
-
-// Single-grid form marching each (i, j) column through a chunk of z-planes (z periodic):
-// the primitive variables of planes k-1, k, k+1 stay in registers, so each plane of the
-// state is read once per chunk for the zeta differences.
-template <typename R>
-__global__ void __launch_bounds__(256) k_nodes_march(StageArgs A, int kchunk) {
-  const Dims& D = A.D;
-  const int i = blockIdx.x * 64 + threadIdx.x, j = blockIdx.y * 4 + threadIdx.y;
-  if (i >= D.n[0] || j >= D.n[1]) return;
-  const int nk = D.n[2], N = (int)D.N;
-  const int kbeg = blockIdx.z * kchunk, kend = min(kbeg + kchunk, nk);
-  const int pl = D.n[0] * D.n[1];
-  const int o0 = i + D.n[0] * j;
-  Prim zm = load_prim(A.q, N, o0 + pl * (kbeg == 0 ? nk - 1 : kbeg - 1), A.P);
-  Prim z0 = load_prim(A.q, N, o0 + pl * kbeg, A.P);
-  for (int k = kbeg; k < kend; ++k) {
-    const Prim zp = load_prim(A.q, N, o0 + pl * (k + 1 == nk ? 0 : k + 1), A.P);
-    // (i, j) pass through an empty asm statement so that the neighbour addresses are formed
-    // on each plane rather than hoisted out of the loop into registers.
-    int il = i, jl = j;
-    if constexpr (sizeof(R) == sizeof(float)) asm volatile("" : "+v"(il), "+v"(jl));
-    node_record<R, true>(A, il, jl, k, zm, z0, zp);
-    zm = z0;
-    z0 = zp;
-  }
-}
-
-// The same march with the in-plane neighbours shared through LDS: each thread forms the
-// primitive variables of its own node once per plane (the queue's upper plane) and threads
-// 0..135 those of the tile's one-node ring; the centred xi and eta differences then read
-// the tile. One-sided differences at the ends of a non-periodic direction read global
-// memory as before.
-template <typename R>
-__global__ void __launch_bounds__(256) k_nodes_tile(StageArgs A, int kchunk) {
-  __shared__ R Lp[4 * kNodeTileN];
+__device__ __forceinline__ void nodes_tile_block(const StageArgs& A, int bx, int by, int kbeg,
+                                                 int kend, R* Lp) {
   const Dims& D = A.D;
   const int ni = D.n[0], nj = D.n[1], nk = D.n[2], N = (int)D.N;
   const int tx = threadIdx.x, ty = threadIdx.y, tid = tx + 64 * ty;
-  const int i0 = blockIdx.x * 64, j0 = blockIdx.y * 4;
+  const int i0 = bx * 64, j0 = by * 4;
   const int i = i0 + tx, j = j0 + ty;
   const bool mine = i < ni && j < nj;
-  const int kbeg = blockIdx.z * kchunk, kend = min(kbeg + kchunk, nk);
   const int pl = ni * nj;
   // Ring slot of this thread (threads 0..135): rows j0 - 1 and j0 + 4, then columns i0 - 1
   // and i0 + 64. A thread whose own node lies past the end of a periodic direction stages
@@ -306,18 +272,22 @@ __global__ void __launch_bounds__(256) k_nodes_tile(StageArgs A, int kchunk) {
 }
 
 template <typename R>
-__global__ void __launch_bounds__(256) k_nodes(StageArgs A) {
-  nodes_block<R>(A, blockIdx.x, blockIdx.y, blockIdx.z);
+__global__ void __launch_bounds__(256) k_nodes_tile(StageArgs A, int kchunk) {
+  __shared__ R Lp[4 * kNodeTileN];
+  const int kbeg = blockIdx.z * kchunk;
+  nodes_tile_block<R>(A, blockIdx.x, blockIdx.y, kbeg, min(kbeg + kchunk, A.D.n[2]), Lp);
 }
 
-// Persistent form over the members of a batch: item = (member, bx, by, k).
+// Persistent form over the members of a batch: item = (member, bx | by << 16, kbeg, kend).
 template <typename R>
-__global__ void __launch_bounds__(256) k_nodes_batch(const StageArgs* __restrict__ args,
-                                                     const int4* __restrict__ work, int nwork) {
+__global__ void __launch_bounds__(256) k_nodes_tile_batch(const StageArgs* __restrict__ args,
+                                                          const int4* __restrict__ work,
+                                                          int nwork) {
+  __shared__ R Lp[4 * kNodeTileN];
   for (int w = blockIdx.x; w < nwork; w += gridDim.x) {
     const int4 it = work[w];
     const StageArgs A = args[it.x];
-    nodes_block<R>(A, it.y, it.z, it.w);
+    nodes_tile_block<R>(A, it.y & 0xffff, it.y >> 16, it.z, it.w, Lp);
   }
 }
 
@@ -899,24 +869,21 @@ k_stage_batch(const StageArgs* __restrict__ args, const int4* __restrict__ work,
 
 }  // namespace
 
+int nodes_kchunk(const Dims& D) {
+  // z-chunks of about 8 planes, at least 2048 blocks in all
+  const int gx = (D.n[0] + 63) / 64, gy = (D.n[1] + 3) / 4;
+  const int nz = std::max(1, std::min(D.n[2], std::max(D.n[2] / 8, 2048 / (gx * gy))));
+  return (D.n[2] + nz - 1) / nz;
+}
+
 hipError_t launch_nodes(const StageArgs& A, hipStream_t s) {
-  dim3 block(64, 4, 1);
   const int gx = (A.D.n[0] + 63) / 64, gy = (A.D.n[1] + 3) / 4;
-  if (A.D.per[2]) {  // march through z-chunks of about 8 planes, at least 2048 blocks in all
-    const int nz = std::max(1, std::min(A.D.n[2], std::max(A.D.n[2] / 8, 2048 / (gx * gy))));
-    const int kchunk = (A.D.n[2] + nz - 1) / nz;
-    const dim3 grid(gx, gy, (A.D.n[2] + kchunk - 1) / kchunk);
-    if (A.mixed)
-      hipLaunchKernelGGL(k_nodes_tile<float>, grid, block, 0, s, A, kchunk);
-    else
-      hipLaunchKernelGGL(k_nodes_tile<double>, grid, block, 0, s, A, kchunk);
-    return hipGetLastError();
-  }
-  dim3 grid(gx, gy, A.D.n[2]);
+  const int kchunk = nodes_kchunk(A.D);
+  const dim3 grid(gx, gy, (A.D.n[2] + kchunk - 1) / kchunk), block(64, 4, 1);
   if (A.mixed)
-    hipLaunchKernelGGL(k_nodes<float>, grid, block, 0, s, A);
+    hipLaunchKernelGGL(k_nodes_tile<float>, grid, block, 0, s, A, kchunk);
   else
-    hipLaunchKernelGGL(k_nodes<double>, grid, block, 0, s, A);
+    hipLaunchKernelGGL(k_nodes_tile<double>, grid, block, 0, s, A, kchunk);
   return hipGetLastError();
 }
 
@@ -989,17 +956,17 @@ hipError_t launch_nodes_batch(const BatchLaunch& B, hipStream_t s) {
   if (B.grid <= 0) {
     int nb = 0;
     hipError_t e = B.mixed
-        ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_nodes_batch<float>, 256, 0)
-        : hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_nodes_batch<double>, 256, 0);
+        ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_nodes_tile_batch<float>, 256, 0)
+        : hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_nodes_tile_batch<double>, 256, 0);
     *B.occupancy = nb;
     return e;
   }
   if (B.mixed)
-    hipLaunchKernelGGL(k_nodes_batch<float>, dim3(B.grid), dim3(64, 4), 0, s, B.args, B.work,
-                       B.nwork);
+    hipLaunchKernelGGL(k_nodes_tile_batch<float>, dim3(B.grid), dim3(64, 4), 0, s, B.args,
+                       B.work, B.nwork);
   else
-    hipLaunchKernelGGL(k_nodes_batch<double>, dim3(B.grid), dim3(64, 4), 0, s, B.args, B.work,
-                       B.nwork);
+    hipLaunchKernelGGL(k_nodes_tile_batch<double>, dim3(B.grid), dim3(64, 4), 0, s, B.args,
+                       B.work, B.nwork);
   return hipGetLastError();
 }
 
