@@ -197,7 +197,7 @@ int build_face_work(les_batch* b) {
   for (int mi = 0; mi < (int)b->m.size(); ++mi) {
     const Dims& D = b->m[mi]->dims;
     const int gx = (D.n[0] + tx - 1) / tx, gy = (D.n[1] + ty - 1) / ty;
-    const int kc = kchunk_for(D, tx, ty, b->kmin);
+    const int kc = kchunk_for(D, tx, ty, b->kmin, 0);
     for (int k0 = 0; k0 < D.n[2]; k0 += kc)
       for (int by = 0; by < gy; ++by)
         for (int bx = 0; bx < gx; ++bx)

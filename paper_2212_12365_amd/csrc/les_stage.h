@@ -53,9 +53,11 @@ extern const char* const kTileNames[kNumTiles];
 hipError_t launch_nodes(const StageArgs& A, hipStream_t s);
 hipError_t launch_stage(const StageArgs& A, hipStream_t s);
 
-// Thread-tile extent of a tile index, and the z-chunk depth the stage launch uses for it.
+// Thread-tile extent of a tile index, and the z-chunk depth of the face kernel for it: at
+// least kmin planes, chosen against the number of blocks resident at once (resident <= 0:
+// chunks for about 1024 blocks, the form the persistent batch work lists use).
 void tile_shape(int tile, int* tx, int* ty);
-int kchunk_for(const Dims& D, int tx, int ty, int kmin);
+int kchunk_for(const Dims& D, int tx, int ty, int kmin, int resident);
 
 // A persistent launch over a batch: `args` holds one StageArgs per member (device), `work`
 // the work items (device). grid <= 0 asks for the kernel's resident blocks per CU instead

@@ -894,7 +894,17 @@ const char* const kTileNames[kNumTiles] = {"32x8", "32x4", "16x8", "16x16", "16x
 template <int TX, int TY, int WPE = 1, typename R = double>
 hipError_t launch_planes(const StageArgs& A, hipStream_t s, int kmin) {
   const int gx = (A.D.n[0] + TX - 1) / TX, gy = (A.D.n[1] + TY - 1) / TY;
-  const int kchunk = kchunk_for(A.D, TX, TY, kmin);
+  // Blocks resident at once on the device (occupancy query, kept after the first call).
+  static int resident = 0;
+  if (resident <= 0) {
+    int per_cu = 0, dev = 0, cus = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_stage_planes<TX, TY, WPE, R>,
+                                                     TX * TY, 0) == hipSuccess &&
+        hipGetDevice(&dev) == hipSuccess &&
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess)
+      resident = per_cu * cus;
+  }
+  const int kchunk = kchunk_for(A.D, TX, TY, kmin, resident);
   const int nz = (A.D.n[2] + kchunk - 1) / kchunk;
   hipLaunchKernelGGL((k_stage_planes<TX, TY, WPE, R>), dim3(gx, gy, nz), dim3(TX * TY), 0, s, A, kchunk);
   return hipGetLastError();
@@ -908,11 +918,29 @@ void tile_shape(int tile, int* tx, int* ty) {
   *ty = shapes[t][1];
 }
 
-int kchunk_for(const Dims& D, int tx, int ty, int kmin) {
+int kchunk_for(const Dims& D, int tx, int ty, int kmin, int resident) {
   const int gx = (D.n[0] + tx - 1) / tx, gy = (D.n[1] + ty - 1) / ty;
-  int nz = (1024 + gx * gy - 1) / (gx * gy);
-  nz = max(1, min(nz, D.n[2] / max(kmin, 1)));
-  return (D.n[2] + nz - 1) / nz;
+  const long long tiles = (long long)gx * gy;
+  const int nk = D.n[2], nzmax = max(1, nk / max(kmin, 1));
+  if (resident <= 0) {  // about 1024 blocks
+    const int nz = max(1, min((int)((1024 + tiles - 1) / tiles), nzmax));
+    return (nk + nz - 1) / nz;
+  }
+  // Every block of a chunk takes about (depth + 1) plane times (the extra plane: the two
+  // zeta faces at the chunk ends, which read their outer node from global memory), and the
+  // blocks run in waves of `resident`: pick the chunk count with the least waves x depth.
+  int best = (nk + nzmax - 1) / nzmax;
+  long long best_cost = -1;
+  for (int nz = 1; nz <= nzmax; ++nz) {
+    const int kc = (nk + nz - 1) / nz;
+    const long long waves = (tiles * ((nk + kc - 1) / kc) + resident - 1) / resident;
+    const long long cost = waves * (kc + 1);
+    if (best_cost < 0 || cost < best_cost) {
+      best_cost = cost;
+      best = kc;
+    }
+  }
+  return best;
 }
 
 namespace {
