@@ -17,7 +17,7 @@ HEADERS = ["les_device.h", "les_common.h", "les_stage.h", "les_bcdt.h", "les_mlp
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
-         "-Wno-unused-command-line-argument", "-ffp-contract=off"]
+         "-Wno-unused-command-line-argument", "-ffp-contract=off", "-Wl,-z,defs"]
 
 
 def build(verbose=False):
