@@ -36,10 +36,15 @@ __device__ __forceinline__ f32x4 mfma16(bf16x8 a, bf16x8 b, f32x4 c) {
 }
 
 // GELU in its tanh form, written through 0.5 (1 + tanh y) = 1 / (1 + exp(-2y)) with the
-// hardware exponential and reciprocal: gelu(x) = x s, s = 1 / (1 + exp(-2 k0 (x + k1 x^3))).
+// hardware exponential and reciprocal (v_exp_f32, v_rcp_f32: about 1 ulp each, far below the
+// BF16 rounding of the products): gelu(x) = x s, s = 1 / (1 + exp(-2 k0 (x + k1 x^3))).
+// With exp(-2y) = 2^(x (c1 + c2 x^2)), c1 = -2 k0 log2(e), c2 = c1 k1, the sigmoid takes a
+// square, one fused multiply-add, a product, the base-2 exponential and a reciprocal.
+constexpr float kGc1 = -2.f * kG0 * 1.4426950408889634f;
+constexpr float kGc2 = kGc1 * kG1;
 __device__ __forceinline__ float gelu_sig(float x) {
-  const float y = kG0 * (x + kG1 * x * x * x);
-  return __frcp_rn(1.f + __expf(-2.f * y));
+  const float u = __builtin_fmaf(kGc2, x * x, kGc1);
+  return __builtin_amdgcn_rcpf(1.f + __builtin_amdgcn_exp2f(x * u));
 }
 
 __device__ __forceinline__ float gelu_f(float x) { return x * gelu_sig(x); }
@@ -166,7 +171,16 @@ __device__ __forceinline__ float forward16(const float* __restrict__ th, const b
 
 // The same forward pass with split-BF16 products (three MFMAs per product: hi*hi, hi*lo,
 // lo*hi) for inference: w1h/w1l, w2h/w2l are the split weights, H and Hl the split h1.
-__device__ __forceinline__ float forward16_split(const float* __restrict__ th,
+// The wave's own LDS rows carry h1 from layer 1 to layer 2; LDS operations of one wave
+// complete in order, so a wave-scope fence (which waits for the writes) replaces a block
+// barrier. bs holds b1, b2, w3 and b3 in LDS.
+__device__ __forceinline__ void wave_lds_fence() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+__device__ __forceinline__ float forward16_split(const float* bs,
                                                  const bf16x8 (&w1h)[4], const bf16x8 (&w1l)[4],
                                                  const bf16x8 (&w2h)[4][2],
                                                  const bf16x8 (&w2l)[4][2], const float* x,
@@ -186,7 +200,7 @@ __device__ __forceinline__ float forward16_split(const float* __restrict__ th,
     bf16x4 hh, hl;
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
-      a[i] += th[kOffB1 + 16 * t + 4 * g + i];
+      a[i] += bs[16 * t + 4 * g + i];
       __bf16 p, q;
       split_bf16(gelu_f(a[i]), p, q);
       hh[i] = p;
@@ -195,7 +209,7 @@ __device__ __forceinline__ float forward16_split(const float* __restrict__ th,
     *(bf16x4*)&H[s * HS + 16 * t + 4 * g] = hh;
     *(bf16x4*)&Hl[s * HS + 16 * t + 4 * g] = hl;
   }
-  __syncthreads();
+  wave_lds_fence();
   float z = 0.f;
 #pragma unroll
   for (int t = 0; t < 4; ++t) {
@@ -210,11 +224,12 @@ __device__ __forceinline__ float forward16_split(const float* __restrict__ th,
     }
 #pragma unroll
     for (int i = 0; i < 4; ++i)
-      z += th[kOffW3 + 16 * t + 4 * g + i] * gelu_f(acc[i] + th[kOffB2 + 16 * t + 4 * g + i]);
+      z += bs[128 + 16 * t + 4 * g + i] * gelu_f(acc[i] + bs[64 + 16 * t + 4 * g + i]);
   }
   z += __shfl_xor(z, 16);
   z += __shfl_xor(z, 32);
-  return z + th[kOffB3];
+  wave_lds_fence();  // this tile's reads of H end before the next tile writes it
+  return z + bs[192];
 }
 
 // ---------------------------------------------------------------------------------------
@@ -238,8 +253,17 @@ struct InferArgs {
 __global__ void __launch_bounds__(256) k_mlp_infer(InferArgs A) {
   __shared__ __attribute__((aligned(16))) __bf16 H[4][16 * HS];
   __shared__ __attribute__((aligned(16))) __bf16 Hl[4][16 * HS];
+  __shared__ __attribute__((aligned(16))) float bs[196];  // b1, b2, w3, b3
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, g = lane >> 4, s = lane & 15;
   const float* __restrict__ th = A.net.theta;
+  if (threadIdx.x < 64) {
+    bs[threadIdx.x] = th[kOffB1 + threadIdx.x];
+    bs[64 + threadIdx.x] = th[kOffB2 + threadIdx.x];
+    bs[128 + threadIdx.x] = th[kOffW3 + threadIdx.x];
+  } else if (threadIdx.x == 64) {
+    bs[192] = th[kOffB3];
+  }
+  __syncthreads();
   bf16x8 w1h[4], w1l[4], w2h[4][2], w2l[4][2];
 #pragma unroll
   for (int t = 0; t < 4; ++t) {
@@ -269,7 +293,7 @@ __global__ void __launch_bounds__(256) k_mlp_infer(InferArgs A) {
       float xs[kMlpIn];
 #pragma unroll
       for (int c = 0; c < kMlpIn; ++c) xs[c] = __shfl(x[c], s + 16 * t);
-      const float z = forward16_split(th, w1h, w1l, w2h, w2l, xs, lane, H[wv], Hl[wv]);
+      const float z = forward16_split(bs, w1h, w1l, w2h, w2l, xs, lane, H[wv], Hl[wv]);
       if (g == t) zmine = z;
     }
     if (id < A.n) {
