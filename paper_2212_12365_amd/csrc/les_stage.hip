@@ -753,7 +753,11 @@ __device__ __forceinline__ void stage_block(const StageArgs& A, int bx, int by, 
       const int s = tf + r * NT;
 #pragma unroll
       for (int c = 0; c < 5; ++c) hx[r][c] = (R)0;
-      const int fx = s % (TX + 1), fy = s / (TX + 1);
+      // Slot 0 (s < NT = TX*TY) takes the first TX faces of each row, a row per TX lanes,
+      // so the lanes of an LDS access read consecutive words; slot 1 the rows' last faces.
+      static_assert(PL::NX <= 2 * NT, "two xi-face slots per thread");
+      int fx = r == 0 ? s % TX : TX, fy = r == 0 ? s / TX : s - NT;
+      if constexpr (sizeof(R) == sizeof(double)) asm volatile("" : "+v"(fx), "+v"(fy));
       const int ia = wrap_or_out(i0 - 1 + fx, ni, D.per[0]);
       const int ja = wrap_or_out(j0 + fy, nj, D.per[1]);
       if (s < PL::NX && ia >= 0 && ja >= 0 && (D.per[0] || ia < ni - 1)) {
@@ -804,9 +808,10 @@ __device__ __forceinline__ void stage_block(const StageArgs& A, int bx, int by, 
 #pragma unroll
     for (int r = 0; r < MX; ++r) {
       const int s = tf + r * NT;
+      const int hs = r == 0 ? s + s / TX : (TX + 1) * (s - NT) + TX;  // row-major index
       if (s < PL::NX)
 #pragma unroll
-        for (int c = 0; c < 5; ++c) L.H[c][s] = hx[r][c];
+        for (int c = 0; c < 5; ++c) L.H[c][hs] = hx[r][c];
     }
 #pragma unroll
     for (int r = 0; r < MY; ++r) {
