@@ -168,9 +168,10 @@ int les_tuning_count(void);
 const char* les_tuning_name(int tile);
 
 /* Instrumentation: with enable != 0, les_step records HIP events on its stream around the
- * two kernels of every Runge-Kutta stage: the node-record kernel (primitives, eddy
- * viscosity, spectral radii, sensors) and the face kernel (fluxes, flux differences and the
- * stage update); boundary conditions and the time-step reduction are excluded.
+ * two kernels of every Runge-Kutta stage: the node-record kernel (eddy viscosity, spectral
+ * radii, sensors; with the learned closure also its inputs and evaluation) and the face
+ * kernel (fluxes, flux differences and the stage update); boundary conditions and the
+ * time-step reduction are excluded.
  * les_profile_read waits for the last recorded event and returns, since the last read (or
  * since les_profile), the summed node-kernel and face-kernel times in milliseconds and the
  * number of timed stages, then resets the record. Either time pointer may be NULL. */

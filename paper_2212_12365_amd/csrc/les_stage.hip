@@ -1,12 +1,13 @@
 // Runge-Kutta stage kernels of the LES residual (gfx950).
 //
 // A stage is two launches:
-//  * k_nodes: one thread per node writes a node record (primitive variables, molecular and
-//    eddy viscosity, scaled spectral radii and pressure sensors); the eddy viscosity and the
-//    sensors read the neighbouring nodes through the cache.
+//  * k_nodes_tile: one thread per (i, j) column marches a chunk of z-planes and writes each
+//    node's record (eddy viscosity, scaled spectral radii, pressure sensors and the centred
+//    zeta differences of u, v, w, T); the in-plane neighbours come from an LDS tile.
 //  * k_stage_planes: one block per column tile marches through a chunk of z-planes, stages
-//    each plane's node data in LDS, computes every face flux of the plane once (paper,
-//    Spatial Discretization), and each node sums its six face fluxes and either writes the
+//    each plane's node data in LDS (forming the primitive variables and the molecular
+//    viscosity from the state), computes every face flux of the plane once (paper, Spatial
+//    Discretization), and each node sums its six face fluxes and either writes the
 //    residual or applies the Runge-Kutta stage update (paper, Time Marching Method).
 // Both run in FP64, or with FP32 face arithmetic in the mixed form.
 #include <hip/hip_runtime.h>
