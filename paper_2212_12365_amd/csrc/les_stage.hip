@@ -564,6 +564,19 @@ __device__ __forceinline__ void stage_block(const StageArgs& A, int bx, int by, 
   constexpr int NDX = (TX + 2) * TY, NDY = TX * (TY + 2);
   constexpr int MDX = (NDX + NT - 1) / NT;  // lb/nu staging slots per thread
   constexpr int MDY = (NDY + NT - 1) / NT;
+  // Face slots: slot 0 of thread t is face t; slot 1 holds the faces NT.. of a direction,
+  // taken by the first lanes of wave WX (xi) or WY (eta). -1: no face.
+  constexpr int NWAVE = NT / 64, WX = 1 % NWAVE, WY = 2 % NWAVE;
+  static_assert(NT % 64 == 0 && MX == 2 && MY == 2 && PL::NX - NT <= 64 && PL::NY - NT <= 64,
+                "face slot layout");
+  auto xi_slot = [](int t, int r) {
+    const int e = t - 64 * WX;
+    return r == 0 ? t : (e >= 0 && e < PL::NX - NT ? NT + e : -1);
+  };
+  auto eta_slot = [](int t, int r) {
+    const int e = t - 64 * WY;
+    return r == 0 ? t : (e >= 0 && e < PL::NY - NT ? NT + e : -1);
+  };
   const Dims& D = A.D;
   const PhysT<R> Ph(A.P);
   const int N = (int)D.N;
@@ -679,7 +692,9 @@ __device__ __forceinline__ void stage_block(const StageArgs& A, int bx, int by, 
       constexpr int M1b = M1 > 1 ? M1 - 1 : 1;
       R vf[M1b][sNF], vdx[MDX][2], vdy[MDY][2];
 #pragma unroll
-      for (int r = 1; r < M1; ++r) load_f(tl + r * NT, vf[r - 1]);
+      // The extra one-ring slots count down from the last thread, so they land on the waves
+      // that the extra two-ring slots (counting up from thread 0) leave idle.
+      for (int r = 1; r < M1; ++r) load_f(r * NT + (NT - 1 - tl), vf[r - 1]);
 #pragma unroll
       for (int r = 0; r < MDX; ++r) {
         const int s = tl + r * NT;
@@ -706,7 +721,7 @@ __device__ __forceinline__ void stage_block(const StageArgs& A, int bx, int by, 
       }
 #pragma unroll
       for (int r = 1; r < M1; ++r) {
-        const int s = tl + r * NT;
+        const int s = r * NT + (NT - 1 - tl);
         if (s < PL::N1)
 #pragma unroll
           for (int c = sMut; c < sNF; ++c) L.in.F[c][s] = vf[r - 1][c];
@@ -747,21 +762,23 @@ __device__ __forceinline__ void stage_block(const StageArgs& A, int bx, int by, 
       }
     }
 
-    // Faces of the plane, held in registers until the staging space is free.
+    // Faces of the plane, held in registers until the staging space is free. Slot 0 of
+    // every thread takes one xi and one eta face; the TY extra xi faces and TX extra eta
+    // faces (slot 1) go to the lanes of two different waves, so that no wave evaluates more
+    // than four faces per plane (the wave with the most faces sets the time to the barrier).
     R hx[MX][5], hy[MY][5];
 #pragma unroll
     for (int r = 0; r < MX; ++r) {
-      const int s = tf + r * NT;
+      const int s = xi_slot(tf, r);
 #pragma unroll
       for (int c = 0; c < 5; ++c) hx[r][c] = (R)0;
       // Slot 0 (s < NT = TX*TY) takes the first TX faces of each row, a row per TX lanes,
       // so the lanes of an LDS access read consecutive words; slot 1 the rows' last faces.
-      static_assert(PL::NX <= 2 * NT, "two xi-face slots per thread");
       int fx = r == 0 ? s % TX : TX, fy = r == 0 ? s / TX : s - NT;
       if constexpr (sizeof(R) == sizeof(double)) asm volatile("" : "+v"(fx), "+v"(fy));
       const int ia = wrap_or_out(i0 - 1 + fx, ni, D.per[0]);
       const int ja = wrap_or_out(j0 + fy, nj, D.per[1]);
-      if (s < PL::NX && ia >= 0 && ja >= 0 && (D.per[0] || ia < ni - 1)) {
+      if (s >= 0 && ia >= 0 && ja >= 0 && (D.per[0] || ia < ni - 1)) {
         const int da = fx + (TX + 2) * fy;
         const LdsNode<TX, TY, 0, R> na{L, fx + PL::RX1 * (fy + 1), (fx + 1) + PL::RX2 * (fy + 2),
                                        L.in.DX[0][da], L.in.DX[1][da]};
@@ -779,13 +796,14 @@ __device__ __forceinline__ void stage_block(const StageArgs& A, int bx, int by, 
     }
 #pragma unroll
     for (int r = 0; r < MY; ++r) {
-      const int s = tf + r * NT;
+      const int s = eta_slot(tf, r);
 #pragma unroll
       for (int c = 0; c < 5; ++c) hy[r][c] = (R)0;
-      const int fx = s % TX, fy = s / TX;
+      int fx = s % TX, fy = s / TX;
+      if constexpr (sizeof(R) == sizeof(double)) asm volatile("" : "+v"(fx), "+v"(fy));
       const int ia = wrap_or_out(i0 + fx, ni, D.per[0]);
       const int ja = wrap_or_out(j0 - 1 + fy, nj, D.per[1]);
-      if (s < PL::NY && ia >= 0 && ja >= 0 && (D.per[1] || ja < nj - 1)) {
+      if (s >= 0 && ia >= 0 && ja >= 0 && (D.per[1] || ja < nj - 1)) {
         const int da = fx + TX * fy;
         const LdsNode<TX, TY, 1, R> na{L, fx + 1 + PL::RX1 * fy, (fx + 2) + PL::RX2 * (fy + 1),
                                        L.in.DY[0][da], L.in.DY[1][da]};
@@ -808,16 +826,16 @@ __device__ __forceinline__ void stage_block(const StageArgs& A, int bx, int by, 
     __syncthreads();  // staging reads done: the space now takes the face fluxes
 #pragma unroll
     for (int r = 0; r < MX; ++r) {
-      const int s = tf + r * NT;
+      const int s = xi_slot(tf, r);
       const int hs = r == 0 ? s + s / TX : (TX + 1) * (s - NT) + TX;  // row-major index
-      if (s < PL::NX)
+      if (s >= 0)
 #pragma unroll
         for (int c = 0; c < 5; ++c) L.H[c][hs] = hx[r][c];
     }
 #pragma unroll
     for (int r = 0; r < MY; ++r) {
-      const int s = tf + r * NT;
-      if (s < PL::NY)
+      const int s = eta_slot(tf, r);
+      if (s >= 0)
 #pragma unroll
         for (int c = 0; c < 5; ++c) L.H[c][PL::NX + s] = hy[r][c];
     }
