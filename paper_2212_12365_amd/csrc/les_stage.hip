@@ -586,7 +586,6 @@ __device__ __forceinline__ void stage_block(const StageArgs& A, int bx, int by, 
   const int a = tid % TX, b = tid / TX;
   const int i = i0 + a, j = j0 + b;
   const bool mine = i < ni && j < nj;
-  const double* __restrict__ q = A.q;
   const R* __restrict__ rec = records_of<R>(A);
   const R* __restrict__ S = metrics_of<R>(A);
 

@@ -549,7 +549,10 @@ int les_init_grid(const les_params* params, const double* xyz, les_ctx** out) {
   c->tile = params->precision == LES_MIXED ? 0 : 3;
   c->n_updated = 1;
   for (int d = 0; d < 3; ++d) c->n_updated *= D.per[d] ? D.n[d] : D.n[d] - 2;
-  hipGetDevice(&c->device);
+  if (hipGetDevice(&c->device) != hipSuccess) {
+    delete c;
+    return LES_EHIP;
+  }
   long long N = D.N;
   int ni = D.n[0], nj = D.n[1], nk = D.n[2];
   double* d_xyz = nullptr;
