@@ -88,11 +88,10 @@ __device__ __forceinline__ NodeState<R> node_state(const StageArgs& A, unsigned 
   return n;
 }
 
-// Node record of one node. Primitive variables are formed in FP64 from the FP64 state;
-// the differences, eddy viscosity, spectral radii and sensors are evaluated in R.
-// Node record of node (i, j, k). With kQueue the primitive variables of the node and of its
-// zeta neighbours (periodic zeta) are given by the caller (zm, z0, zp); otherwise they are
-// loaded here.
+// Node record of node (i, j, k). Primitive variables are formed in FP64 from the FP64
+// state; the differences, eddy viscosity, spectral radii and sensors are evaluated in R.
+// With kQueue the primitive variables of the node and of its zeta neighbours (periodic
+// zeta) are given by the caller (zm, z0, zp); otherwise they are loaded here.
 // With nl non-null, the centred xi and eta neighbours' u, v, w, p come from a plane tile in
 // LDS: nl[f * kNodeTileN + npos +- 1] along xi and +- kNodeTileX along eta (f = u, v, w, p).
 constexpr int kNodeTileX = 66, kNodeTileY = 6, kNodeTileN = kNodeTileX * kNodeTileY;
@@ -318,7 +317,7 @@ struct PlaneLds {
   static constexpr int NW = RX2 * RY2, N1 = RX1 * RY1;
   static constexpr int NX = (TX + 1) * TY, NY = TX * (TY + 1);
   // Staging of one plane. Once its faces are computed the same space holds the face
-  // fluxes (xi then eta), 5 * (NX + NY) doubles.
+  // fluxes (xi then eta), 5 * (NX + NY) values.
   union {
     struct {
       R W[6][NW];    // W0..W4 and p over the two-node ring
@@ -357,8 +356,9 @@ struct LdsNode {
   }
 };
 
-// Face inputs of node (i, j, k) from global memory (zeta faces), with centred xi and eta
-// differences.
+// Face inputs of node (i, j, k) from global memory (the zeta faces at the ends of a chunk):
+// the state-derived inputs are formed from the state as in the staging, the others read
+// from the records, metrics and J^-1; xi and eta differences are centred.
 template <typename R>
 struct GlobalNodeZ {
   const StageArgs& A;
