@@ -512,12 +512,12 @@ int les_batch_autotune(les_batch* b, double* const* q, int* tile_out, int* kmin_
                      t, b->mixed, nullptr};
       float ms = INFINITY;
       for (int rep = 0; rep < 3 && !rc; ++rep) {
-        hipEventRecord(e0, s);
-        if (launch_stage_batch(Lf, s) != hipSuccess) rc = LES_EHIP;
-        hipEventRecord(e1, s);
-        if (hipEventSynchronize(e1) != hipSuccess) rc = LES_EHIP;
+        if (hipEventRecord(e0, s) != hipSuccess) rc = LES_EHIP;
+        if (!rc && launch_stage_batch(Lf, s) != hipSuccess) rc = LES_EHIP;
+        if (!rc && hipEventRecord(e1, s) != hipSuccess) rc = LES_EHIP;
+        if (!rc && hipEventSynchronize(e1) != hipSuccess) rc = LES_EHIP;
         float x = 0.f;
-        hipEventElapsedTime(&x, e0, e1);
+        if (!rc && hipEventElapsedTime(&x, e0, e1) != hipSuccess) rc = LES_EHIP;
         if (rep > 0) ms = std::min(ms, x);  // the first launch warms the caches
       }
       if (!rc && ms < best) {

@@ -191,16 +191,15 @@ __device__ __forceinline__ float forward16_split(const float* bs,
   for (int i = 0; i < 8; ++i) xv[i] = (g == 0 && i < kMlpIn) ? x[i] : 0.f;
   bf16x8 bxh, bxl;
   split_frag(xv, bxh, bxl);
-  const f32x4 zero = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
   for (int t = 0; t < 4; ++t) {
-    f32x4 a = mfma16(w1l[t], bxh, zero);
+    // The bias seeds the accumulator.
+    f32x4 a = mfma16(w1l[t], bxh, *(const f32x4*)&bs[16 * t + 4 * g]);
     a = mfma16(w1h[t], bxl, a);
     a = mfma16(w1h[t], bxh, a);
     bf16x4 hh, hl;
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
-      a[i] += bs[16 * t + 4 * g + i];
       __bf16 p, q;
       split_bf16(gelu_f(a[i]), p, q);
       hh[i] = p;
@@ -213,7 +212,7 @@ __device__ __forceinline__ float forward16_split(const float* bs,
   float z = 0.f;
 #pragma unroll
   for (int t = 0; t < 4; ++t) {
-    f32x4 acc = zero;
+    f32x4 acc = *(const f32x4*)&bs[64 + 16 * t + 4 * g];  // the bias seeds the accumulator
 #pragma unroll
     for (int kb = 0; kb < 2; ++kb) {
       const bf16x8 bh = *(const bf16x8*)&H[s * HS + 32 * kb + 8 * g];
@@ -223,8 +222,7 @@ __device__ __forceinline__ float forward16_split(const float* bs,
       acc = mfma16(w2h[t][kb], bh, acc);
     }
 #pragma unroll
-    for (int i = 0; i < 4; ++i)
-      z += bs[128 + 16 * t + 4 * g + i] * gelu_f(acc[i] + bs[64 + 16 * t + 4 * g + i]);
+    for (int i = 0; i < 4; ++i) z += bs[128 + 16 * t + 4 * g + i] * gelu_f(acc[i]);
   }
   z += __shfl_xor(z, 16);
   z += __shfl_xor(z, 32);

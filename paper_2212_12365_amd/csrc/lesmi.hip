@@ -329,11 +329,6 @@ __global__ void k_rhs_norm_final(const double* __restrict__ part, int nparts, do
   out[1] = mx;
 }
 
-__global__ void k_copy(long long n, const double* __restrict__ src, double* __restrict__ dst) {
-  long long id = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (id < n) dst[id] = src[id];
-}
-
 // ---------------------------------------------------------------------------------------
 // Host side.
 // ---------------------------------------------------------------------------------------
