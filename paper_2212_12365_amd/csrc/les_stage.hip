@@ -614,7 +614,7 @@ __device__ __forceinline__ void stage_block(const StageArgs& A, int bx, int by, 
     // from it are then formed anew on each plane instead of being hoisted out of the loop
     // (where they would hold registers across the face arithmetic).
     int tl = tid;
-    if constexpr (sizeof(R) == sizeof(double)) asm volatile("" : "+v"(tl));
+    asm volatile("" : "+v"(tl));
     // Staging loads of slot s of the two-node ring (W and p) and of the one-node ring (the
     // other face inputs); nodes outside a non-periodic range stage zeros.
     // A slot of the two-node ring inside the one-node ring also supplies that ring's u, v,
@@ -746,7 +746,7 @@ __device__ __forceinline__ void stage_block(const StageArgs& A, int bx, int by, 
 
     // Zeta face between planes k-1 and k, and the update of the node on plane k-1.
     int tf = tid;  // laundered again for the face phase
-    if constexpr (sizeof(R) == sizeof(double)) asm volatile("" : "+v"(tf));
+    asm volatile("" : "+v"(tf));
     const int own1 = tf % TX + 1 + PL::RX1 * (tf / TX + 1);
     const int own2 = tf % TX + 2 + PL::RX2 * (tf / TX + 2);
     if (pending) {
@@ -774,7 +774,7 @@ __device__ __forceinline__ void stage_block(const StageArgs& A, int bx, int by, 
       // Slot 0 (s < NT = TX*TY) takes the first TX faces of each row, a row per TX lanes,
       // so the lanes of an LDS access read consecutive words; slot 1 the rows' last faces.
       int fx = r == 0 ? s % TX : TX, fy = r == 0 ? s / TX : s - NT;
-      if constexpr (sizeof(R) == sizeof(double)) asm volatile("" : "+v"(fx), "+v"(fy));
+      asm volatile("" : "+v"(fx), "+v"(fy));
       const int ia = wrap_or_out(i0 - 1 + fx, ni, D.per[0]);
       const int ja = wrap_or_out(j0 + fy, nj, D.per[1]);
       if (s >= 0 && ia >= 0 && ja >= 0 && (D.per[0] || ia < ni - 1)) {
@@ -799,7 +799,7 @@ __device__ __forceinline__ void stage_block(const StageArgs& A, int bx, int by, 
 #pragma unroll
       for (int c = 0; c < 5; ++c) hy[r][c] = (R)0;
       int fx = s % TX, fy = s / TX;
-      if constexpr (sizeof(R) == sizeof(double)) asm volatile("" : "+v"(fx), "+v"(fy));
+      asm volatile("" : "+v"(fx), "+v"(fy));
       const int ia = wrap_or_out(i0 + fx, ni, D.per[0]);
       const int ja = wrap_or_out(j0 - 1 + fy, nj, D.per[1]);
       if (s >= 0 && ia >= 0 && ja >= 0 && (D.per[1] || ja < nj - 1)) {
