@@ -32,6 +32,10 @@ def case(name):
         xyz, sh = skewed_periodic_grid((24, 20, 18))
         p = sy.box_params((24, 20, 18), sh, re_acoustic=200.0, cs=0.18)
         return p, xyz, smooth_field(xyz, p.gamma, seed=1)
+    if name == "skew_odd":  # ragged tiles in every direction, wraps past the grid's end
+        xyz, sh = skewed_periodic_grid((37, 22, 9))
+        p = sy.box_params((37, 22, 9), sh, re_acoustic=150.0, cs=0.18)
+        return p, xyz, smooth_field(xyz, p.gamma, seed=7)
     if name.startswith("jet"):
         shapes = {"jet_small": (64, 48, 32), "jet_ragged": (37, 21, 12),
                   "jet_c2": (256, 128, 128)}

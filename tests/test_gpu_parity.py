@@ -32,7 +32,7 @@ def _announce(what):
     print(f"[gpu] {what}", flush=True)
 
 
-CASES = ["box4", "tgv32", "skew24", "jet_ragged", "jet_small"]
+CASES = ["box4", "tgv32", "skew24", "skew_odd", "jet_ragged", "jet_small"]
 
 
 @pytest.mark.parametrize("name", CASES)
@@ -100,7 +100,7 @@ def test_apply_bc(torch, name):
 
 
 @pytest.mark.parametrize("name,nsteps", [("tgv32", 20), ("skew24", 5), ("jet_small", 5),
-                                         ("jet_ragged", 8)])
+                                         ("jet_ragged", 8), ("skew_odd", 6)])
 def test_step(torch, name, nsteps):
     _announce(f"step {name} x{nsteps}")
     p, xyz, q = case(name)
