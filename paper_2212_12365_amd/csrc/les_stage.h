@@ -38,6 +38,13 @@ struct StageArgs {
   const double* q0;
   const double* dt;
   double alpha;
+  // Time-step reduction in the node kernel (FP64 form only; null: off): each updated node
+  // contributes J^-1 / (sum of its three spectral radii), the same operations on the same
+  // values as the separate reduction; block b of the node kernel writes its minimum to
+  // dtpart[b], and a non-positive density or pressure or a non-finite ratio sets bit 2 of
+  // *flag.
+  double* dtpart;
+  int* flag;
   int tile;   // k_stage_planes tile shape, index into kTileNames
   int kmin;   // smallest z-chunk depth (0 = default)
   // Learned closure (k_nodes): inputs [6][N], scale rho Delta^2 |S| [N] and |S| [N] of the
@@ -51,6 +58,8 @@ constexpr int kNumTiles = 10;
 extern const char* const kTileNames[kNumTiles];
 
 hipError_t launch_nodes(const StageArgs& A, hipStream_t s);
+// Number of blocks of the node kernel (the partial minima of its time-step reduction).
+int nodes_blocks(const Dims& D);
 hipError_t launch_stage(const StageArgs& A, hipStream_t s);
 
 // Thread-tile extent of a tile index, and the z-chunk depth of the face kernel for it: at

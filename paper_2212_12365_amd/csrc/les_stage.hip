@@ -99,7 +99,8 @@ constexpr int kNodeTileX = 66, kNodeTileY = 6, kNodeTileN = kNodeTileX * kNodeTi
 template <typename R, bool kQueue>
 __device__ __forceinline__ void node_record(const StageArgs& A, int i, int j, int k,
                                             const Prim& zm, const Prim& z0, const Prim& zp,
-                                            const R* nl = nullptr, int npos = 0) {
+                                            const R* nl = nullptr, int npos = 0,
+                                            double* rdt = nullptr) {
   const Dims& D = A.D;
   const PhysT<R> P(A.P);
   const int N = (int)D.N;
@@ -163,6 +164,12 @@ __device__ __forceinline__ void node_record(const StageArgs& A, int i, int j, in
   const R l0 = spectral<R>(sm[0], sm[1], sm[2], su, sv, sw, a);
   const R l1 = spectral<R>(sm[3], sm[4], sm[5], su, sv, sw, a);
   const R l2 = spectral<R>(sm[6], sm[7], sm[8], su, sv, sw, a);
+  if constexpr (sizeof(R) == sizeof(double))
+    if (rdt && is_updated(D, i, j, k)) {  // the node's term of the time-step reduction
+      const double r = jinv / (l0 + l1 + l2);
+      if (!(s.rho > 0.0) || !(s.p > 0.0) || !isfinite(r)) atomicOr(A.flag, 2);
+      *rdt = fmin(*rdt, r);
+    }
   R lb[3];
   scaled_radii<R>(l0, l1, l2, lb);
   R* __restrict__ r = records_of<R>(A);
@@ -198,7 +205,7 @@ __device__ __forceinline__ void node_record(const StageArgs& A, int i, int j, in
 // so the centred xi and eta differences read the tile and each node's primitive variables
 // are formed about 1.5 times per plane. One-sided differences at the ends of a non-periodic
 // direction read global memory.
-template <typename R>
+template <typename R, bool kDt = false>
 __device__ __forceinline__ void nodes_tile_block(const StageArgs& A, int bx, int by, int kbeg,
                                                  int kend, R* Lp) {
   const Dims& D = A.D;
@@ -232,6 +239,7 @@ __device__ __forceinline__ void nodes_tile_block(const StageArgs& A, int bx, int
     if (oki && okj) wo = (i % ni) + ni * (j % nj);
   }
   const int o0 = i + ni * j;
+  double rdt = INFINITY;  // this column's minimum of the time-step reduction
   Prim zm{}, z0{};
   if (mine) {
     zm = load_prim(A.q, N, o0 + pl * (kbeg == 0 ? nk - 1 : kbeg - 1), A.P);
@@ -265,17 +273,29 @@ __device__ __forceinline__ void nodes_tile_block(const StageArgs& A, int bx, int
     // each plane instead of holding registers across the loop.
     int il = i, jl = j, ol = own;
     asm volatile("" : "+v"(il), "+v"(jl), "+v"(ol));
-    if (mine) node_record<R, true>(A, il, jl, k, zm, z0, zp, Lp, ol);
+    if (mine) node_record<R, true>(A, il, jl, k, zm, z0, zp, Lp, ol, kDt ? &rdt : nullptr);
     zm = z0;
     z0 = zp;
   }
+  if constexpr (kDt) {  // the block's minimum (the tile is free now)
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) rdt = fmin(rdt, __shfl_xor(rdt, o));
+    __syncthreads();
+    double* red = (double*)Lp;
+    if ((tid & 63) == 0) red[tid >> 6] = rdt;
+    __syncthreads();
+    if (tid == 0)
+      A.dtpart[blockIdx.x + gridDim.x * (blockIdx.y + gridDim.y * blockIdx.z)] =
+          fmin(fmin(red[0], red[1]), fmin(red[2], red[3]));
+  }
 }
 
-template <typename R>
+// kDt: also the time-step reduction's block minima (FP64, A.dtpart).
+template <typename R, bool kDt = false>
 __global__ void __launch_bounds__(256) k_nodes_tile(StageArgs A, int kchunk) {
   __shared__ R Lp[4 * kNodeTileN];
   const int kbeg = blockIdx.z * kchunk;
-  nodes_tile_block<R>(A, blockIdx.x, blockIdx.y, kbeg, min(kbeg + kchunk, A.D.n[2]), Lp);
+  nodes_tile_block<R, kDt>(A, blockIdx.x, blockIdx.y, kbeg, min(kbeg + kchunk, A.D.n[2]), Lp);
 }
 
 // Persistent form over the members of a batch: item = (member, bx | by << 16, kbeg, kend).
@@ -899,12 +919,19 @@ int nodes_kchunk(const Dims& D) {
   return (D.n[2] + nz - 1) / nz;
 }
 
+int nodes_blocks(const Dims& D) {
+  const int kchunk = nodes_kchunk(D);
+  return ((D.n[0] + 63) / 64) * ((D.n[1] + 3) / 4) * ((D.n[2] + kchunk - 1) / kchunk);
+}
+
 hipError_t launch_nodes(const StageArgs& A, hipStream_t s) {
   const int gx = (A.D.n[0] + 63) / 64, gy = (A.D.n[1] + 3) / 4;
   const int kchunk = nodes_kchunk(A.D);
   const dim3 grid(gx, gy, (A.D.n[2] + kchunk - 1) / kchunk), block(64, 4, 1);
   if (A.mixed)
     hipLaunchKernelGGL(k_nodes_tile<float>, grid, block, 0, s, A, kchunk);
+  else if (A.dtpart)
+    hipLaunchKernelGGL((k_nodes_tile<double, true>), grid, block, 0, s, A, kchunk);
   else
     hipLaunchKernelGGL(k_nodes_tile<double>, grid, block, 0, s, A, kchunk);
   return hipGetLastError();

@@ -488,14 +488,20 @@ int prof_mark(les_ctx* c, hipStream_t s) {
 
 // One residual evaluation: node records, then faces and flux differences with either the
 // residual (mode 0) or the Runge-Kutta stage update (mode 1) as the epilogue.
+// With cfl > 0 (FP64 form), the node kernel also reduces the time step of this stage's
+// input (its block minima, then k_dt_final) before the face kernel uses it.
 int run_stage(les_ctx* c, const double* q, int mode, double* out, const double* q0,
-              double alpha, hipStream_t s) {
+              double alpha, hipStream_t s, double cfl = 0.0) {
   StageArgs A = stage_args(c, q);
   A.mode = mode;
   A.out = out;
   A.q0 = q0;
   A.dt = c->d_dt;
   A.alpha = alpha;
+  if (cfl > 0.0) {
+    A.dtpart = c->d_dtpart;
+    A.flag = c->d_flag;
+  }
   const bool timed = mode == 1;
   int rc = timed ? prof_mark(c, s) : LES_OK;
   if (rc) return rc;
@@ -503,6 +509,11 @@ int run_stage(les_ctx* c, const double* q, int mode, double* out, const double* 
   if (e == hipSuccess && c->params.closure == LES_MLP) e = run_mlp_closure(c, nullptr, s);
   if (e == hipSuccess && timed) rc = prof_mark(c, s);
   if (rc) return rc;
+  if (e == hipSuccess && cfl > 0.0) {
+    hipLaunchKernelGGL(k_dt_final, dim3(1), dim3(256), 0, s, c->d_dtpart,
+                       nodes_blocks(c->dims), cfl, c->d_dt);
+    e = hipGetLastError();
+  }
   if (e == hipSuccess) e = launch_stage(A, s);
   if (e == hipSuccess && timed) rc = prof_mark(c, s);
   if (rc) return rc;
@@ -656,20 +667,22 @@ int les_step(les_ctx* c, double* q, int nsteps, double cfl, double dt_fixed, dou
   hipStream_t s = (hipStream_t)stream;
   const Dims& D = c->dims;
   hipLaunchKernelGGL(k_set_int, dim3(1), dim3(1), 0, s, c->d_flag, 0);
+  // The FP64 form reduces the time step inside the first stage's node kernel.
+  const bool fused_dt = cfl > 0.0 && c->params.precision == LES_FP64;
   for (int n = 0; n < nsteps; ++n) {
-    if (cfl > 0.0) {
+    if (cfl > 0.0 && !fused_dt) {
       dim3 ng = node_grid(D);
       hipLaunchKernelGGL(k_dt_partial, ng, dim3(64, 4), 0, s, D, c->phys, q, c->S, c->jinv,
                          c->d_dtpart, c->d_flag);
       hipLaunchKernelGGL(k_dt_final, dim3(1), dim3(256), 0, s, c->d_dtpart,
                          (int)(ng.x * ng.y * ng.z), cfl, c->d_dt);
-    } else {
+    } else if (!(cfl > 0.0)) {
       hipLaunchKernelGGL(k_set_scalar, dim3(1), dim3(1), 0, s, c->d_dt, dt_fixed);
     }
     const double* in = q;
     for (int l = 0; l < 5; ++l) {
       double* outb = (l == 4) ? q : ((l % 2 == 0) ? c->qa : c->qb);
-      int rc = run_stage(c, in, 1, outb, q, kAlpha[l], s);
+      int rc = run_stage(c, in, 1, outb, q, kAlpha[l], s, (l == 0 && fused_dt) ? cfl : 0.0);
       if (rc) return rc;
       rc = run_bc(c, outb, s);
       if (rc) return rc;
