@@ -38,11 +38,10 @@ struct StageArgs {
   const double* q0;
   const double* dt;
   double alpha;
-  // Time-step reduction in the node kernel (FP64 form only; null: off): each updated node
-  // contributes J^-1 / (sum of its three spectral radii), the same operations on the same
-  // values as the separate reduction; block b of the node kernel writes its minimum to
-  // dtpart[b], and a non-positive density or pressure or a non-finite ratio sets bit 2 of
-  // *flag.
+  // Time-step reduction in the node kernel (null: off): each updated node contributes
+  // J^-1 / (sum of its three spectral radii) in FP64, the same operations on the same values
+  // as the separate reduction; block b of the node kernel writes its minimum to dtpart[b],
+  // and a non-positive density or pressure or a non-finite ratio sets bit 2 of *flag.
   double* dtpart;
   int* flag;
   int tile;   // k_stage_planes tile shape, index into kTileNames

@@ -164,12 +164,21 @@ __device__ __forceinline__ void node_record(const StageArgs& A, int i, int j, in
   const R l0 = spectral<R>(sm[0], sm[1], sm[2], su, sv, sw, a);
   const R l1 = spectral<R>(sm[3], sm[4], sm[5], su, sv, sw, a);
   const R l2 = spectral<R>(sm[6], sm[7], sm[8], su, sv, sw, a);
-  if constexpr (sizeof(R) == sizeof(double))
-    if (rdt && is_updated(D, i, j, k)) {  // the node's term of the time-step reduction
-      const double r = jinv / (l0 + l1 + l2);
-      if (!(s.rho > 0.0) || !(s.p > 0.0) || !isfinite(r)) atomicOr(A.flag, 2);
-      *rdt = fmin(*rdt, r);
+  if (rdt && is_updated(D, i, j, k)) {  // the node's term of the time-step reduction
+    double l;
+    if constexpr (sizeof(R) == sizeof(double)) {
+      l = l0 + l1 + l2;
+    } else {  // in FP64 from the FP64 metrics, as the separate reduction takes it
+      const double* __restrict__ S64 = A.S;
+      const double a64 = sqrt(s.T);
+      l = spectral(S64[o], S64[N + o], S64[2 * N + o], s.u, s.v, s.w, a64) +
+          spectral(S64[3 * N + o], S64[4 * N + o], S64[5 * N + o], s.u, s.v, s.w, a64) +
+          spectral(S64[6 * N + o], S64[7 * N + o], S64[8 * N + o], s.u, s.v, s.w, a64);
     }
+    const double r = A.jinv[o] / l;
+    if (!(s.rho > 0.0) || !(s.p > 0.0) || !isfinite(r)) atomicOr(A.flag, 2);
+    *rdt = fmin(*rdt, r);
+  }
   R lb[3];
   scaled_radii<R>(l0, l1, l2, lb);
   R* __restrict__ r = records_of<R>(A);
@@ -290,7 +299,7 @@ __device__ __forceinline__ void nodes_tile_block(const StageArgs& A, int bx, int
   }
 }
 
-// kDt: also the time-step reduction's block minima (FP64, A.dtpart).
+// kDt: also the time-step reduction's block minima (A.dtpart).
 template <typename R, bool kDt = false>
 __global__ void __launch_bounds__(256) k_nodes_tile(StageArgs A, int kchunk) {
   __shared__ R Lp[4 * kNodeTileN];
@@ -928,7 +937,9 @@ hipError_t launch_nodes(const StageArgs& A, hipStream_t s) {
   const int gx = (A.D.n[0] + 63) / 64, gy = (A.D.n[1] + 3) / 4;
   const int kchunk = nodes_kchunk(A.D);
   const dim3 grid(gx, gy, (A.D.n[2] + kchunk - 1) / kchunk), block(64, 4, 1);
-  if (A.mixed)
+  if (A.mixed && A.dtpart)
+    hipLaunchKernelGGL((k_nodes_tile<float, true>), grid, block, 0, s, A, kchunk);
+  else if (A.mixed)
     hipLaunchKernelGGL(k_nodes_tile<float>, grid, block, 0, s, A, kchunk);
   else if (A.dtpart)
     hipLaunchKernelGGL((k_nodes_tile<double, true>), grid, block, 0, s, A, kchunk);

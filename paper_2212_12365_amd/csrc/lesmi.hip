@@ -488,8 +488,8 @@ int prof_mark(les_ctx* c, hipStream_t s) {
 
 // One residual evaluation: node records, then faces and flux differences with either the
 // residual (mode 0) or the Runge-Kutta stage update (mode 1) as the epilogue.
-// With cfl > 0 (FP64 form), the node kernel also reduces the time step of this stage's
-// input (its block minima, then k_dt_final) before the face kernel uses it.
+// With cfl > 0, the node kernel also reduces the time step of this stage's input (its block
+// minima, then k_dt_final) before the face kernel uses it.
 int run_stage(les_ctx* c, const double* q, int mode, double* out, const double* q0,
               double alpha, hipStream_t s, double cfl = 0.0) {
   StageArgs A = stage_args(c, q);
@@ -667,8 +667,8 @@ int les_step(les_ctx* c, double* q, int nsteps, double cfl, double dt_fixed, dou
   hipStream_t s = (hipStream_t)stream;
   const Dims& D = c->dims;
   hipLaunchKernelGGL(k_set_int, dim3(1), dim3(1), 0, s, c->d_flag, 0);
-  // The FP64 form reduces the time step inside the first stage's node kernel.
-  const bool fused_dt = cfl > 0.0 && c->params.precision == LES_FP64;
+  // The time step is reduced inside the first stage's node kernel.
+  const bool fused_dt = cfl > 0.0;
   for (int n = 0; n < nsteps; ++n) {
     if (cfl > 0.0 && !fused_dt) {
       dim3 ng = node_grid(D);
