@@ -37,19 +37,6 @@ constexpr int kRows = 6;  // stage rows 0..4 of a step, then the residual row of
 // ---------------------------------------------------------------------------------------
 // Persistent kernels. Items are int4: (member, ...).
 // ---------------------------------------------------------------------------------------
-__global__ void __launch_bounds__(256) k_batch_dt_partial(const StageArgs* __restrict__ row0,
-                                                          const MemberArgs* __restrict__ M,
-                                                          const int4* __restrict__ work,
-                                                          int nwork) {
-  __shared__ double red[256];
-  for (int w = blockIdx.x; w < nwork; w += gridDim.x) {
-    const int4 it = work[w];  // (member, bx | by << 16, k, slot)
-    const MemberArgs& m = M[it.x];
-    dt_block(m.D, m.P, row0[it.x].q, m.S, m.jinv, it.y & 0xffff, it.y >> 16, it.z,
-             m.dtpart + it.w, m.flag, red);
-  }
-}
-
 __global__ void __launch_bounds__(256) k_batch_dt_final(const MemberArgs* __restrict__ M,
                                                         double cfl) {
   __shared__ double red[256];
@@ -138,8 +125,8 @@ struct les_batch {
   // Work lists: node kernel (tile, z-chunk), checks (64 x 4 block, plane), face kernel,
   // axis means, boundary nodes, time-step partials.
   int4 *d_wnodes = nullptr, *d_wcheck = nullptr, *d_wfaces = nullptr, *d_waxis = nullptr,
-       *d_wbc = nullptr, *d_wdt = nullptr;
-  int nwnodes = 0, nwcheck = 0, nwfaces = 0, nwaxis = 0, nwbc = 0, nwdt = 0;
+       *d_wbc = nullptr;
+  int nwnodes = 0, nwcheck = 0, nwfaces = 0, nwaxis = 0, nwbc = 0;
   double* d_dts = nullptr;
   int* d_flags = nullptr;
 
@@ -210,24 +197,22 @@ int build_face_work(les_batch* b) {
 }
 
 int build_static_work(les_batch* b) {
-  std::vector<int4> wn, wc, wa, wb, wd;
+  std::vector<int4> wn, wc, wa, wb;
   std::vector<MemberArgs> mem;
   for (int mi = 0; mi < (int)b->m.size(); ++mi) {
     les_ctx* c = b->m[mi];
     const Dims& D = c->dims;
     const int gx = (D.n[0] + 63) / 64, gy = (D.n[1] + 3) / 4;
-    int slot = 0;
     for (int k = 0; k < D.n[2]; ++k)
       for (int by = 0; by < gy; ++by)
-        for (int bx = 0; bx < gx; ++bx) {
-          wc.push_back(make_int4(mi, bx, by, k));
-          wd.push_back(make_int4(mi, bx | (by << 16), k, slot++));
-        }
+        for (int bx = 0; bx < gx; ++bx) wc.push_back(make_int4(mi, bx, by, k));
     const int kc = nodes_kchunk(D);
+    int slot = 0;  // the member's node items number its time-step partial minima
     for (int k0 = 0; k0 < D.n[2]; k0 += kc)
       for (int by = 0; by < gy; ++by)
         for (int bx = 0; bx < gx; ++bx)
-          wn.push_back(make_int4(mi, bx | (by << 16), k0, std::min(k0 + kc, D.n[2])));
+          wn.push_back(make_int4(mi, bx | (by << 16), k0 | (std::min(k0 + kc, D.n[2]) << 16),
+                                 slot++));
     if (D.jet) {
       for (int i = 1; i <= D.n[0] - 2; ++i) wa.push_back(make_int4(mi, i, 0, 0));
       long long nbc = 2LL * (D.n[0] - 2) * D.n[2] + 2LL * D.n[1] * D.n[2];
@@ -250,12 +235,10 @@ int build_static_work(les_batch* b) {
   b->occ_nodes = occupancy_of(b, false);
   b->nwaxis = (int)wa.size();
   b->nwbc = (int)wb.size();
-  b->nwdt = (int)wd.size();
   BHIP(b, upload(&b->d_wnodes, wn));
   BHIP(b, upload(&b->d_wcheck, wc));
   BHIP(b, upload(&b->d_waxis, wa));
   BHIP(b, upload(&b->d_wbc, wb));
-  BHIP(b, upload(&b->d_wdt, wd));
   BHIP(b, upload(&b->d_mem, mem));
   return LES_OK;
 }
@@ -279,6 +262,8 @@ int bake_args(les_batch* b, double* const* q) {
       A.q0 = q[mi];
       A.dt = c->d_dt;
       A.alpha = kAlpha[l];
+      A.dtpart = c->d_dtpart;  // the first stage's node kernel reduces the time step
+      A.flag = c->d_flag;
       rows[(size_t)l * n + mi] = A;
       in = out;
     }
@@ -300,12 +285,16 @@ int check_launch(les_batch* b, const char* what) {
   return LES_OK;
 }
 
-int enqueue_stage_kernels(les_batch* b, int row, hipStream_t s) {
+// With cfl > 0 the node kernel also reduces each member's time step from this stage's input
+// (block minima, then k_batch_dt_final) before the face kernel uses it.
+int enqueue_stage_kernels(les_batch* b, int row, hipStream_t s, double cfl = 0.0) {
   const int n = (int)b->m.size();
   const StageArgs* args = b->d_args + (size_t)row * n;
   BatchLaunch Ln{args, b->d_wnodes, b->nwnodes, persistent_grid(b, b->occ_nodes, b->nwnodes),
                  b->tile, b->mixed, nullptr};
+  Ln.dt = cfl > 0.0;
   BHIP(b, launch_nodes_batch(Ln, s));
+  if (cfl > 0.0) hipLaunchKernelGGL(k_batch_dt_final, dim3(n), dim3(256), 0, s, b->d_mem, cfl);
   BatchLaunch Lf{args, b->d_wfaces, b->nwfaces, persistent_grid(b, b->occ_faces, b->nwfaces),
                  b->tile, b->mixed, nullptr};
   BHIP(b, launch_stage_batch(Lf, s));
@@ -316,17 +305,12 @@ int enqueue_stage_kernels(les_batch* b, int row, hipStream_t s) {
 int enqueue_step(les_batch* b, double cfl, double dt_fixed, hipStream_t s) {
   const int n = (int)b->m.size();
   const int small = persistent_grid(b, 4, std::max(b->nwaxis, b->nwbc));
-  if (cfl > 0.0) {
-    hipLaunchKernelGGL(k_batch_dt_partial, dim3(persistent_grid(b, 4, b->nwdt)), dim3(64, 4), 0,
-                       s, b->d_args, b->d_mem, b->d_wdt, b->nwdt);
-    hipLaunchKernelGGL(k_batch_dt_final, dim3(n), dim3(256), 0, s, b->d_mem, cfl);
-  } else {
+  if (!(cfl > 0.0))
     hipLaunchKernelGGL(k_batch_set_dt, dim3((n + 63) / 64), dim3(64), 0, s, b->d_mem, n, dt_fixed);
-  }
   int rc = check_launch(b, "batch time step");
   if (rc) return rc;
   for (int l = 0; l < 5; ++l) {
-    rc = enqueue_stage_kernels(b, l, s);
+    rc = enqueue_stage_kernels(b, l, s, l == 0 ? cfl : 0.0);
     if (rc) return rc;
     if (b->nwaxis) {
       const StageArgs* row = b->d_args + (size_t)l * n;
@@ -543,7 +527,7 @@ void les_batch_destroy(les_batch* b) {
   drop_graph(b);
   if (b->cap) (void)hipStreamDestroy(b->cap);
   void* ptrs[] = {b->d_args, b->d_mem, b->d_wnodes, b->d_wcheck, b->d_wfaces,
-                  b->d_waxis, b->d_wbc, b->d_wdt,    b->d_dts,    b->d_flags};
+                  b->d_waxis, b->d_wbc, b->d_dts,    b->d_flags};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
   delete b;

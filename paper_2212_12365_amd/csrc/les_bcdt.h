@@ -171,39 +171,6 @@ __device__ __forceinline__ void bc_node(const Dims& D, const Phys& P, const BcDa
   for (int c = 0; c < 5; ++c) q[(long long)c * N + id] = qo[c];
 }
 
-// ---------------------------------------------------------------------------------------
-// Time step: dt = CFL min over updated nodes of J^-1 / sum_d Lam_d; block minima, then one
-// block reduces them (min is exact whatever the order).
-// ---------------------------------------------------------------------------------------
-// Minimum over one 64 x 4 block of plane k, written to *slot; red is 256 doubles of LDS.
-__device__ __forceinline__ void dt_block(const Dims& D, const Phys& P, const double* __restrict__ q,
-                                         const double* __restrict__ S,
-                                         const double* __restrict__ jinv, int bx, int by, int k,
-                                         double* __restrict__ slot, int* __restrict__ flag,
-                                         double* red) {
-  const int i = bx * 64 + threadIdx.x, j = by * 4 + threadIdx.y;
-  const int tid = threadIdx.x + 64 * threadIdx.y;
-  double r = INFINITY;
-  if (i < D.n[0] && j < D.n[1] && is_updated(D, i, j, k)) {
-    const int N = (int)D.N;
-    const int id = i + D.n[0] * (j + D.n[1] * k);
-    Prim s = prim_from_q(q[id], q[N + id], q[2 * N + id], q[3 * N + id], q[4 * N + id], P);
-    double a = sqrt(s.T);
-    double l = spectral(S[id], S[N + id], S[2 * N + id], s.u, s.v, s.w, a) +
-               spectral(S[3 * N + id], S[4 * N + id], S[5 * N + id], s.u, s.v, s.w, a) +
-               spectral(S[6 * N + id], S[7 * N + id], S[8 * N + id], s.u, s.v, s.w, a);
-    r = jinv[id] / l;
-    if (!(s.rho > 0.0) || !(s.p > 0.0) || !isfinite(r)) atomicOr(flag, 2);
-  }
-  red[tid] = r;
-  __syncthreads();
-  for (int o = 128; o > 0; o >>= 1) {
-    if (tid < o) red[tid] = fmin(red[tid], red[tid + o]);
-    __syncthreads();
-  }
-  if (tid == 0) *slot = red[0];
-  __syncthreads();
-}
 
 // dt = CFL times the minimum of the block minima (exact in any order).
 __device__ __forceinline__ void dt_final_block(const double* __restrict__ part, int nparts,

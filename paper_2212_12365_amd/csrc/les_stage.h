@@ -78,9 +78,12 @@ struct BatchLaunch {
   int tile;
   bool mixed;
   int* occupancy;
+  // Node kernel only: also write each item's time-step partial minimum (StageArgs::dtpart
+  // of its member, at the item's slot).
+  bool dt = false;
 };
-// Node-kernel items are (member, bx | by << 16, kbeg, kend) over 64 x 4 column tiles and
-// z-chunks of nodes_kchunk planes.
+// Node-kernel items are (member, bx | by << 16, kbeg | kend << 16, slot) over 64 x 4 column
+// tiles and z-chunks of nodes_kchunk planes; slot numbers the member's items.
 hipError_t launch_nodes_batch(const BatchLaunch& B, hipStream_t s);
 int nodes_kchunk(const Dims& D);
 

@@ -216,7 +216,7 @@ __device__ __forceinline__ void node_record(const StageArgs& A, int i, int j, in
 // direction read global memory.
 template <typename R, bool kDt = false>
 __device__ __forceinline__ void nodes_tile_block(const StageArgs& A, int bx, int by, int kbeg,
-                                                 int kend, R* Lp) {
+                                                 int kend, R* Lp, int slot = 0) {
   const Dims& D = A.D;
   const int ni = D.n[0], nj = D.n[1], nk = D.n[2], N = (int)D.N;
   const int tx = threadIdx.x, ty = threadIdx.y, tid = tx + 64 * ty;
@@ -293,9 +293,7 @@ __device__ __forceinline__ void nodes_tile_block(const StageArgs& A, int bx, int
     double* red = (double*)Lp;
     if ((tid & 63) == 0) red[tid >> 6] = rdt;
     __syncthreads();
-    if (tid == 0)
-      A.dtpart[blockIdx.x + gridDim.x * (blockIdx.y + gridDim.y * blockIdx.z)] =
-          fmin(fmin(red[0], red[1]), fmin(red[2], red[3]));
+    if (tid == 0) A.dtpart[slot] = fmin(fmin(red[0], red[1]), fmin(red[2], red[3]));
   }
 }
 
@@ -304,11 +302,13 @@ template <typename R, bool kDt = false>
 __global__ void __launch_bounds__(256) k_nodes_tile(StageArgs A, int kchunk) {
   __shared__ R Lp[4 * kNodeTileN];
   const int kbeg = blockIdx.z * kchunk;
-  nodes_tile_block<R, kDt>(A, blockIdx.x, blockIdx.y, kbeg, min(kbeg + kchunk, A.D.n[2]), Lp);
+  nodes_tile_block<R, kDt>(A, blockIdx.x, blockIdx.y, kbeg, min(kbeg + kchunk, A.D.n[2]), Lp,
+                           blockIdx.x + gridDim.x * (blockIdx.y + gridDim.y * blockIdx.z));
 }
 
-// Persistent form over the members of a batch: item = (member, bx | by << 16, kbeg, kend).
-template <typename R>
+// Persistent form over the members of a batch: item = (member, bx | by << 16,
+// kbeg | kend << 16, slot of the member's time-step partial minima).
+template <typename R, bool kDt = false>
 __global__ void __launch_bounds__(256) k_nodes_tile_batch(const StageArgs* __restrict__ args,
                                                           const int4* __restrict__ work,
                                                           int nwork) {
@@ -316,7 +316,7 @@ __global__ void __launch_bounds__(256) k_nodes_tile_batch(const StageArgs* __res
   for (int w = blockIdx.x; w < nwork; w += gridDim.x) {
     const int4 it = work[w];
     const StageArgs A = args[it.x];
-    nodes_tile_block<R>(A, it.y & 0xffff, it.y >> 16, it.z, it.w, Lp);
+    nodes_tile_block<R, kDt>(A, it.y & 0xffff, it.y >> 16, it.z & 0xffff, it.z >> 16, Lp, it.w);
   }
 }
 
@@ -1050,12 +1050,15 @@ hipError_t launch_nodes_batch(const BatchLaunch& B, hipStream_t s) {
     *B.occupancy = nb;
     return e;
   }
-  if (B.mixed)
-    hipLaunchKernelGGL(k_nodes_tile_batch<float>, dim3(B.grid), dim3(64, 4), 0, s, B.args,
-                       B.work, B.nwork);
+  const dim3 g(B.grid), blk(64, 4);
+  if (B.mixed && B.dt)
+    hipLaunchKernelGGL((k_nodes_tile_batch<float, true>), g, blk, 0, s, B.args, B.work, B.nwork);
+  else if (B.mixed)
+    hipLaunchKernelGGL(k_nodes_tile_batch<float>, g, blk, 0, s, B.args, B.work, B.nwork);
+  else if (B.dt)
+    hipLaunchKernelGGL((k_nodes_tile_batch<double, true>), g, blk, 0, s, B.args, B.work, B.nwork);
   else
-    hipLaunchKernelGGL(k_nodes_tile_batch<double>, dim3(B.grid), dim3(64, 4), 0, s, B.args,
-                       B.work, B.nwork);
+    hipLaunchKernelGGL(k_nodes_tile_batch<double>, g, blk, 0, s, B.args, B.work, B.nwork);
   return hipGetLastError();
 }
 

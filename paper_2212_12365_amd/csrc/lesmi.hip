@@ -185,16 +185,6 @@ __global__ void k_bc(Dims D, Phys P, BcData B, double* __restrict__ q) {
   bc_node(D, P, B, q, (long long)blockIdx.x * blockDim.x + threadIdx.x);
 }
 
-__global__ void __launch_bounds__(256) k_dt_partial(Dims D, Phys P, const double* __restrict__ q,
-                                                    const double* __restrict__ S,
-                                                    const double* __restrict__ jinv,
-                                                    double* __restrict__ part,
-                                                    int* __restrict__ flag) {
-  __shared__ double red[256];
-  dt_block(D, P, q, S, jinv, blockIdx.x, blockIdx.y, blockIdx.z,
-           part + blockIdx.x + gridDim.x * (blockIdx.y + gridDim.y * blockIdx.z), flag, red);
-}
-
 __global__ void __launch_bounds__(256) k_dt_final(const double* __restrict__ part, int nparts,
                                                   double cfl, double* __restrict__ dt) {
   __shared__ double red[256];
@@ -667,22 +657,13 @@ int les_step(les_ctx* c, double* q, int nsteps, double cfl, double dt_fixed, dou
   hipStream_t s = (hipStream_t)stream;
   const Dims& D = c->dims;
   hipLaunchKernelGGL(k_set_int, dim3(1), dim3(1), 0, s, c->d_flag, 0);
-  // The time step is reduced inside the first stage's node kernel.
-  const bool fused_dt = cfl > 0.0;
   for (int n = 0; n < nsteps; ++n) {
-    if (cfl > 0.0 && !fused_dt) {
-      dim3 ng = node_grid(D);
-      hipLaunchKernelGGL(k_dt_partial, ng, dim3(64, 4), 0, s, D, c->phys, q, c->S, c->jinv,
-                         c->d_dtpart, c->d_flag);
-      hipLaunchKernelGGL(k_dt_final, dim3(1), dim3(256), 0, s, c->d_dtpart,
-                         (int)(ng.x * ng.y * ng.z), cfl, c->d_dt);
-    } else if (!(cfl > 0.0)) {
-      hipLaunchKernelGGL(k_set_scalar, dim3(1), dim3(1), 0, s, c->d_dt, dt_fixed);
-    }
+    // With cfl > 0 the time step is reduced inside the first stage's node kernel.
+    if (!(cfl > 0.0)) hipLaunchKernelGGL(k_set_scalar, dim3(1), dim3(1), 0, s, c->d_dt, dt_fixed);
     const double* in = q;
     for (int l = 0; l < 5; ++l) {
       double* outb = (l == 4) ? q : ((l % 2 == 0) ? c->qa : c->qb);
-      int rc = run_stage(c, in, 1, outb, q, kAlpha[l], s, (l == 0 && fused_dt) ? cfl : 0.0);
+      int rc = run_stage(c, in, 1, outb, q, kAlpha[l], s, (l == 0 && cfl > 0.0) ? cfl : 0.0);
       if (rc) return rc;
       rc = run_bc(c, outb, s);
       if (rc) return rc;
