@@ -271,9 +271,10 @@ int les_batch_step(les_batch* b, double* const* q, int nsteps, double cfl, doubl
 int les_batch_set_tuning(les_batch* b, int tile, int kmin);
 int les_batch_get_tuning(const les_batch* b, int* tile, int* kmin);
 
-/* Autotuner of the batch: times every tile shape with z-chunk depths 4, 8 and 16 on one
- * persistent residual launch over all members (states q, not modified) and keeps the
- * fastest. Synchronises the stream. */
+/* Autotuner of the batch: times every tile shape with z-chunk depths 4, 8 and 16 on the
+ * first two Runge-Kutta stages of all members with dt = 0 (the states q are read, not
+ * modified; the members' stage buffers are overwritten) and keeps the fastest.
+ * Synchronises the stream. */
 int les_batch_autotune(les_batch* b, double* const* q, int* tile, int* kmin, void* stream);
 
 /* enable != 0 (the default): steps replay a captured graph; 0: launches are issued one by

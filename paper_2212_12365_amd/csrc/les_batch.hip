@@ -477,32 +477,31 @@ int les_batch_autotune(les_batch* b, double* const* q, int* tile_out, int* kmin_
   if (rc) return rc;
   static const int kmins[] = {4, 8, 16};
   const int n = (int)b->m.size();
-  const StageArgs* res = b->d_args + (size_t)5 * n;
+  drop_graph(b);  // the candidates replace the work list a captured step refers to
   hipEvent_t e0, e1;
   BHIP(b, hipEventCreate(&e0));
   BHIP(b, hipEventCreate(&e1));
   float best = INFINITY;
   int bt = b->tile, bk = b->kmin;
-  BatchLaunch Ln{res, b->d_wnodes, b->nwnodes, persistent_grid(b, b->occ_nodes, b->nwnodes), 0,
-                 b->mixed, nullptr};
-  rc = launch_nodes_batch(Ln, s) == hipSuccess ? LES_OK : LES_EHIP;
+  // Each candidate runs the first two stages of a step (node and stage kernels): they read
+  // q and write only the context buffers qa and qb, with dt = 0.
+  hipLaunchKernelGGL(k_batch_set_dt, dim3((n + 63) / 64), dim3(64), 0, s, b->d_mem, n, 0.0);
+  rc = check_launch(b, "autotune");
   for (int t = 0; !rc && t < kNumTiles; ++t)
     for (int km : kmins) {
       b->tile = t;
       b->kmin = km;
       rc = build_face_work(b);
       if (rc) break;
-      BatchLaunch Lf{res, b->d_wfaces, b->nwfaces, persistent_grid(b, b->occ_faces, b->nwfaces),
-                     t, b->mixed, nullptr};
       float ms = INFINITY;
-      for (int rep = 0; rep < 3 && !rc; ++rep) {
+      for (int rep = 0; rep < 4 && !rc; ++rep) {
         if (hipEventRecord(e0, s) != hipSuccess) rc = LES_EHIP;
-        if (!rc && launch_stage_batch(Lf, s) != hipSuccess) rc = LES_EHIP;
+        for (int l = 0; l < 2 && !rc; ++l) rc = enqueue_stage_kernels(b, l, s);
         if (!rc && hipEventRecord(e1, s) != hipSuccess) rc = LES_EHIP;
         if (!rc && hipEventSynchronize(e1) != hipSuccess) rc = LES_EHIP;
         float x = 0.f;
         if (!rc && hipEventElapsedTime(&x, e0, e1) != hipSuccess) rc = LES_EHIP;
-        if (rep > 0) ms = std::min(ms, x);  // the first launch warms the caches
+        if (rep > 0) ms = std::min(ms, x);  // the first run warms the caches
       }
       if (!rc && ms < best) {
         best = ms;
