@@ -548,16 +548,18 @@ __device__ __forceinline__ void face_eval(const NA& a, const NB& b, const R* Wm,
 // Residual of node (i, j, k) from the sum of its xi and eta face differences (part) and its
 // zeta faces above (hu) and below (hd): written out (mode 0) or applied as the Runge-Kutta
 // stage update Q = Q0 - alpha dt J R (mode 1). Nodes that are not updated get a zero
-// residual in mode 0 and are left alone in mode 1.
+// residual in mode 0 and are left alone in mode 1. pq and pj, when given, are the node's
+// Q0 and J loaded earlier by the caller.
 template <typename R>
 __device__ __forceinline__ void finish_node(const StageArgs& A, int i, int j, int k,
-                                            const R* part, const R* hu, const R* hd) {
+                                            const R* part, const R* hu, const R* hd,
+                                            const double* pq = nullptr, double pj = 0.0) {
   const Dims& D = A.D;
   const int N = (int)D.N;
   const int o = i + D.n[0] * (j + D.n[1] * k);
   if (is_updated(D, i, j, k)) {
     double fac = 0.0;
-    if (A.mode == 1) fac = A.alpha * A.dt[0] * A.jac[o];
+    if (A.mode == 1) fac = A.alpha * A.dt[0] * (pq ? pj : A.jac[o]);
 #pragma unroll
     for (int c = 0; c < 5; ++c) {
       R rr = part[c];
@@ -565,7 +567,7 @@ __device__ __forceinline__ void finish_node(const StageArgs& A, int i, int j, in
       if (A.mode == 0)
         A.out[c * N + o] = (double)rr;
       else
-        A.out[c * N + o] = A.q0[c * N + o] - fac * (double)rr;
+        A.out[c * N + o] = (pq ? pq[c] : A.q0[c * N + o]) - fac * (double)rr;
     }
   } else if (A.mode == 0) {
 #pragma unroll
@@ -683,6 +685,15 @@ __device__ __forceinline__ void stage_block(const StageArgs& A, int bx, int by, 
     // spectral radius and sensor, and W one plane above the own node (outer node of the
     // pending zeta face).
     R zl[2] = {0, 0}, wp[5] = {0, 0, 0, 0, 0};
+    // Q^(0) and J of the pending node for its stage update, loaded with the staging so that
+    // their latency is hidden behind it rather than exposed after the zeta face.
+    double pq[5] = {0, 0, 0, 0, 0}, pj = 0.0;
+    if (pending && A.mode == 1) {
+      const unsigned o1 = (unsigned)(i + ni * (j + nj * (k - 1)));
+#pragma unroll
+      for (int c = 0; c < 5; ++c) pq[c] = A.q0[c * N + o1];
+      pj = A.jac[o1];
+    }
     {
       R vw[MW][11], vf[sNF];
 #pragma unroll
@@ -782,7 +793,7 @@ __device__ __forceinline__ void stage_block(const StageArgs& A, int bx, int by, 
       const LdsNode<TX, TY, 2, R> nb{L, own1, own2, zl[0], zl[1]};
       R hz[5];
       face_eval<2, R>(lo, nb, Wm, wp, k - 1, nk, true, Ph, hz);
-      finish_node<R>(A, i, j, k - 1, part, hz, hz_lo);
+      finish_node<R>(A, i, j, k - 1, part, hz, hz_lo, pq, pj);
 #pragma unroll
       for (int c = 0; c < 5; ++c) {
         hz_lo[c] = hz[c];
