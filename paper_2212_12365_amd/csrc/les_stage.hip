@@ -595,6 +595,9 @@ __device__ __forceinline__ void stage_block(const StageArgs& A, int bx, int by, 
   constexpr int NDX = (TX + 2) * TY, NDY = TX * (TY + 2);
   constexpr int MDX = (NDX + NT - 1) / NT;  // lb/nu staging slots per thread
   constexpr int MDY = (NDY + NT - 1) / NT;
+  // FP64 loads the xi/eta lb and nu with the first staging group; in the mixed form they
+  // go with the second, since the first would take the kernel past 168 VGPRs (3 waves/SIMD).
+  constexpr bool kDxyEarly = sizeof(R) == sizeof(double);
   // Face slots: slot 0 of thread t is face t; slot 1 holds the faces NT.. of a direction,
   // taken by the first lanes of wave WX (xi) or WY (eta). -1: no face.
   constexpr int NWAVE = NT / 64, WX = 1 % NWAVE, WY = 2 % NWAVE;
@@ -680,10 +683,55 @@ __device__ __forceinline__ void stage_block(const StageArgs& A, int bx, int by, 
         for (int c = 0; c < 4; ++c) v[sDz + c] = rec[(kRecDz + c) * N + o];
       }
     };
+    // Scaled spectral radius and sensor of the xi- and eta-face nodes (DX, DY).
+    auto load_dxy = [&](R(&vdx)[MDX][2], R(&vdy)[MDY][2]) {
+#pragma unroll
+      for (int r = 0; r < MDX; ++r) {
+        const int s = tl + r * NT;
+        const int ia = wrap_or_out(i0 - 1 + s % (TX + 2), ni, D.per[0]);
+        const int ja = wrap_or_out(j0 + s / (TX + 2), nj, D.per[1]);
+        vdx[r][0] = vdx[r][1] = (R)0;
+        if (s < NDX && ia >= 0 && ja >= 0) {
+          const unsigned o = (unsigned)(ia + ni * (ja + nj * k));
+          vdx[r][0] = rec[kRecLb * N + o];
+          vdx[r][1] = rec[kRecNu * N + o];
+        }
+      }
+#pragma unroll
+      for (int r = 0; r < MDY; ++r) {
+        const int s = tl + r * NT;
+        const int ia = wrap_or_out(i0 + s % TX, ni, D.per[0]);
+        const int ja = wrap_or_out(j0 - 1 + s / TX, nj, D.per[1]);
+        vdy[r][0] = vdy[r][1] = (R)0;
+        if (s < NDY && ia >= 0 && ja >= 0) {
+          const unsigned o = (unsigned)(ia + ni * (ja + nj * k));
+          vdy[r][0] = rec[(kRecLb + 1) * N + o];
+          vdy[r][1] = rec[(kRecNu + 1) * N + o];
+        }
+      }
+    };
+    auto write_dxy = [&](const R(&vdx)[MDX][2], const R(&vdy)[MDY][2]) {
+#pragma unroll
+      for (int r = 0; r < MDX; ++r) {
+        const int s = tl + r * NT;
+        if (s < NDX) {
+          L.in.DX[0][s] = vdx[r][0];
+          L.in.DX[1][s] = vdx[r][1];
+        }
+      }
+#pragma unroll
+      for (int r = 0; r < MDY; ++r) {
+        const int s = tl + r * NT;
+        if (s < NDY) {
+          L.in.DY[0][s] = vdy[r][0];
+          L.in.DY[1][s] = vdy[r][1];
+        }
+      }
+    };
     // The plane is staged in two groups of loads, each written to LDS as it arrives.
     // Group 1: the two-node ring, the first slot of the one-node ring, the own node's zeta
-    // spectral radius and sensor, and W one plane above the own node (outer node of the
-    // pending zeta face).
+    // spectral radius and sensor, W one plane above the own node (outer node of the
+    // pending zeta face), and in FP64 the xi/eta lb and nu.
     R zl[2] = {0, 0}, wp[5] = {0, 0, 0, 0, 0};
     // Q^(0) and J of the pending node for its stage update, loaded with the staging so that
     // their latency is hidden behind it rather than exposed after the zeta face.
@@ -695,10 +743,11 @@ __device__ __forceinline__ void stage_block(const StageArgs& A, int bx, int by, 
       pj = A.jac[o1];
     }
     {
-      R vw[MW][11], vf[sNF];
+      R vw[MW][11], vf[sNF], vdx[MDX][2], vdy[MDY][2];
 #pragma unroll
       for (int r = 0; r < MW; ++r) load_w(tl + r * NT, vw[r]);
       load_f(tl, vf);
+      if constexpr (kDxyEarly) load_dxy(vdx, vdy);
       if (mine) {
         const unsigned o = (unsigned)(i + ni * (j + nj * k));
         zl[0] = rec[(kRecLb + 2) * N + o];
@@ -724,9 +773,10 @@ __device__ __forceinline__ void stage_block(const StageArgs& A, int bx, int by, 
       if (tl < PL::N1)
 #pragma unroll
         for (int c = sMut; c < sNF; ++c) L.in.F[c][tl] = vf[c];
+      if constexpr (kDxyEarly) write_dxy(vdx, vdy);
     }
-    // Group 2: the other slots of the one-node ring, and the scaled spectral radius and
-    // sensor of the xi- and eta-face nodes.
+    // Group 2: the other slots of the one-node ring, and in the mixed form the xi/eta lb
+    // and nu.
     {
       constexpr int M1b = M1 > 1 ? M1 - 1 : 1;
       R vf[M1b][sNF], vdx[MDX][2], vdy[MDY][2];
@@ -734,30 +784,7 @@ __device__ __forceinline__ void stage_block(const StageArgs& A, int bx, int by, 
       // The extra one-ring slots count down from the last thread, so they land on the waves
       // that the extra two-ring slots (counting up from thread 0) leave idle.
       for (int r = 1; r < M1; ++r) load_f(r * NT + (NT - 1 - tl), vf[r - 1]);
-#pragma unroll
-      for (int r = 0; r < MDX; ++r) {
-        const int s = tl + r * NT;
-        const int ia = wrap_or_out(i0 - 1 + s % (TX + 2), ni, D.per[0]);
-        const int ja = wrap_or_out(j0 + s / (TX + 2), nj, D.per[1]);
-        vdx[r][0] = vdx[r][1] = (R)0;
-        if (s < NDX && ia >= 0 && ja >= 0) {
-          const unsigned o = (unsigned)(ia + ni * (ja + nj * k));
-          vdx[r][0] = rec[kRecLb * N + o];
-          vdx[r][1] = rec[kRecNu * N + o];
-        }
-      }
-#pragma unroll
-      for (int r = 0; r < MDY; ++r) {
-        const int s = tl + r * NT;
-        const int ia = wrap_or_out(i0 + s % TX, ni, D.per[0]);
-        const int ja = wrap_or_out(j0 - 1 + s / TX, nj, D.per[1]);
-        vdy[r][0] = vdy[r][1] = (R)0;
-        if (s < NDY && ia >= 0 && ja >= 0) {
-          const unsigned o = (unsigned)(ia + ni * (ja + nj * k));
-          vdy[r][0] = rec[(kRecLb + 1) * N + o];
-          vdy[r][1] = rec[(kRecNu + 1) * N + o];
-        }
-      }
+      if constexpr (!kDxyEarly) load_dxy(vdx, vdy);
 #pragma unroll
       for (int r = 1; r < M1; ++r) {
         const int s = r * NT + (NT - 1 - tl);
@@ -765,22 +792,7 @@ __device__ __forceinline__ void stage_block(const StageArgs& A, int bx, int by, 
 #pragma unroll
           for (int c = sMut; c < sNF; ++c) L.in.F[c][s] = vf[r - 1][c];
       }
-#pragma unroll
-      for (int r = 0; r < MDX; ++r) {
-        const int s = tl + r * NT;
-        if (s < NDX) {
-          L.in.DX[0][s] = vdx[r][0];
-          L.in.DX[1][s] = vdx[r][1];
-        }
-      }
-#pragma unroll
-      for (int r = 0; r < MDY; ++r) {
-        const int s = tl + r * NT;
-        if (s < NDY) {
-          L.in.DY[0][s] = vdy[r][0];
-          L.in.DY[1][s] = vdy[r][1];
-        }
-      }
+      if constexpr (!kDxyEarly) write_dxy(vdx, vdy);
     }
     __syncthreads();
 
@@ -904,6 +916,18 @@ __device__ __forceinline__ void stage_block(const StageArgs& A, int bx, int by, 
   }
 }
 
+// Minimum waves per EU asked of the compiler for the persistent batch kernels: the launch
+// shape's hint, and at least 3 in the mixed form, whose batch kernels otherwise come out a
+// few registers above the 168 of 3 waves; never more than the block's LDS lets a CU
+// (160 KB) hold. (The single-grid mixed kernels reach 3 waves unasked, and measured slower
+// when asked.)
+template <int TX, int TY, int WPE, typename R>
+constexpr int min_waves() {
+  constexpr int want = sizeof(R) == sizeof(float) && WPE < 3 ? 3 : WPE;
+  constexpr int lds = (160 * 1024 / (int)sizeof(PlaneLds<TX, TY, R>)) * (TX * TY / 64) / 4;
+  return want < lds ? want : (lds > 1 ? lds : 1);
+}
+
 template <int TX, int TY, int WPE, typename R>
 __global__ void __launch_bounds__(TX * TY) __attribute__((amdgpu_waves_per_eu(WPE, 8)))
 k_stage_planes(StageArgs A, int kchunk) {
@@ -920,8 +944,9 @@ k_stage_planes(StageArgs A, int kchunk) {
 // The grid is a multiple of 8 blocks, so block b stays on XCD b % 8 and its items, remapped
 // by xcd_tile, form one contiguous run of the work list per XCD.
 template <int TX, int TY, int WPE, typename R>
-__global__ void __launch_bounds__(TX * TY) __attribute__((amdgpu_waves_per_eu(WPE, 8)))
-k_stage_batch(const StageArgs* __restrict__ args, const int4* __restrict__ work, int nwork) {
+__global__ void __launch_bounds__(TX * TY)
+    __attribute__((amdgpu_waves_per_eu(min_waves<TX, TY, WPE, R>(), 8)))
+    k_stage_batch(const StageArgs* __restrict__ args, const int4* __restrict__ work, int nwork) {
   __shared__ PlaneLds<TX, TY, R> L;
   for (int w = blockIdx.x; w < nwork; w += gridDim.x) {
     const int4 it = work[xcd_tile(w, nwork)];
