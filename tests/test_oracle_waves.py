@@ -20,15 +20,19 @@ import pytest
 
 import oracle
 import synthetic as sy
+from golden_data import paper_constants
 from synthetic.grids import cartesian_grid
+
+
+# The five stage coefficients as the paper states them (Time Marching Method).
+ALPHAS = tuple(paper_constants()["rk_alpha"])
 
 
 def P5(z):
     # Nested form of the five-stage scheme applied to dq/dt = (L) q:
     # q1 = 1 + a1 z, q2 = 1 + a2 z q1, ... ; independent of the oracle's C code.
-    alphas = (0.25, 1.0 / 6.0, 0.375, 0.5, 1.0)
     q = 1.0
-    for a in alphas:
+    for a in ALPHAS:
         q = 1.0 + a * z * q
     return q
 
