@@ -219,6 +219,9 @@ def main():
                     help="RK steps of the oracle timed for the CPU baseline (0 = skip)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a 1 GiB device copy (counter calibration) and exit")
+    ap.add_argument("--mixed-only", action="store_true",
+                    help="only time the mixed-precision form of the jet workload and print its "
+                         "figures (for counter runs of its kernels), then exit")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -235,6 +238,14 @@ def main():
     import synthetic as sy
 
     params, xyz, q = sy.make_case("jet", JET_GRID, seed=0)
+    if args.mixed_only:
+        mx = run_form(torch, params.replace(precision=1), xyz, q, args.steps, args.warmup)
+        print(json.dumps({"form": "mixed", "workload": "jet 256x128x128 mixed, CFL 0.5",
+                          "value": round(mx["rate"], 3), "unit": "Mcell-RKstage/s",
+                          "face_kernel_us": round(mx["faces_ms"] * 1e3 / max(mx["stages"], 1), 2),
+                          "node_kernel_us": round(mx["nodes_ms"] * 1e3 / max(mx["stages"], 1), 2)}),
+              flush=True)
+        return
     f64 = run_form(torch, params, xyz, q, args.steps, args.warmup)
     upd = f64["updated_nodes"]
     value = f64["rate"]
