@@ -29,6 +29,10 @@ HBM_PEAK_GBS = 8000.0
 BYTES_PER_CELL_STAGE = {"fp64": (160.0 + 4 * 200.0) / 5.0, "mixed": (124.0 + 4 * 164.0) / 5.0}
 STAGE_SOURCES = ["paper_2212_12365_amd/csrc/les_stage.hip", "paper_2212_12365_amd/csrc/les_device.h"]
 JET_GRID = (256, 128, 128)
+# The meshes of the paper's mesh table (Computational Performance Assessment), as (n_xi,
+# n_eta, n_zeta) = axial, radial and azimuthal points, in the table's order (meshes 1-10).
+PAPER_MESHES = [(200, 150, 40), (400, 150, 40), (800, 150, 40), (400, 75, 40), (400, 300, 40),
+                (400, 150, 10), (400, 150, 60), (800, 300, 120), (200, 75, 40), (200, 75, 20)]
 
 
 def stage_kernel_hash():
@@ -89,6 +93,23 @@ def run_form(torch, params, xyz, q, steps, warmup):
     ctx.close()
     return {"updated_nodes": upd, "wall_s": wall, "nodes_ms": nodes_ms, "faces_ms": faces_ms,
             "stages": stages, "rate": upd * 5 * steps / wall / 1e6}
+
+
+def mesh_sweep(torch, steps, warmup):
+    """FP64 and mixed-form throughput of the synthetic jet on each of the paper's meshes."""
+    import synthetic as sy
+    rows = []
+    for m, n in enumerate(PAPER_MESHES, 1):
+        p, xyz, q = sy.make_case("jet", n, seed=0)
+        f64 = run_form(torch, p, xyz, q, steps, warmup)
+        mx = run_form(torch, p.replace(precision=1), xyz, q, steps, warmup)
+        row = {"mesh": m, "grid": list(n), "nodes": n[0] * n[1] * n[2],
+               "fp64": round(f64["rate"], 1), "mixed": round(mx["rate"], 1),
+               "fp64_face_kernel_us": round(f64["faces_ms"] * 1e3 / max(f64["stages"], 1), 2),
+               "fp64_node_kernel_us": round(f64["nodes_ms"] * 1e3 / max(f64["stages"], 1), 2)}
+        print(json.dumps(row), file=sys.stderr, flush=True)
+        rows.append(row)
+    return rows
 
 
 def run_batched(torch, steps, warmup):
@@ -219,6 +240,9 @@ def main():
                     help="RK steps of the oracle timed for the CPU baseline (0 = skip)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a 1 GiB device copy (counter calibration) and exit")
+    ap.add_argument("--mesh-sweep", action="store_true",
+                    help="only time the FP64 and mixed forms of the jet on the paper's ten "
+                         "meshes (its mesh table) and print one JSON line, then exit")
     ap.add_argument("--mixed-only", action="store_true",
                     help="only time the mixed-precision form of the jet workload and print its "
                          "figures (for counter runs of its kernels), then exit")
@@ -237,6 +261,12 @@ def main():
 
     import synthetic as sy
 
+    if args.mesh_sweep:
+        rows = mesh_sweep(torch, args.steps, args.warmup)
+        print(json.dumps({"mesh_sweep": rows, "unit": "Mcell-RKstage/s", "steps": args.steps,
+                          "warmup": args.warmup, "workload": "synthetic jet, CFL 0.5, Smagorinsky"}),
+              flush=True)
+        return
     params, xyz, q = sy.make_case("jet", JET_GRID, seed=0)
     if args.mixed_only:
         mx = run_form(torch, params.replace(precision=1), xyz, q, args.steps, args.warmup)
