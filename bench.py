@@ -56,6 +56,17 @@ def measured_traffic(kernel_hash):
     return rec.get("bytes_per_launch")
 
 
+def host_cpu():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def cpu_baseline(params, xyz, q, steps):
     import oracle
     threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
@@ -64,12 +75,21 @@ def cpu_baseline(params, xyz, q, steps):
     t0 = time.perf_counter()
     o.step(q, steps, cfl=0.5)
     t = time.perf_counter() - t0
+    # One step again on a single thread.
+    oracle.set_threads(1)
+    t1 = time.perf_counter()
+    o.step(q, 1, cfl=0.5)
+    t1 = time.perf_counter() - t1
+    oracle.set_threads(threads)
     upd = (params.ni - 2) * (params.nj - 2) * params.nk
     return {"value": round(upd * 5 * steps / t / 1e6, 3), "unit": "Mcell-RKstage/s",
             "cores": threads, "kind": "oracle",
             "sample": f"{steps} RK steps (= {5 * steps} stages, with time-step reduction and "
                       f"boundary conditions) of the same jet {params.ni}x{params.nj}x{params.nk} "
-                      f"FP64 workload, {t:.1f} s on {threads} OpenMP threads"}
+                      f"FP64 workload, {t:.1f} s on {threads} OpenMP threads; then 1 step on "
+                      f"1 thread, {t1:.1f} s",
+            "single_thread_value": round(upd * 5 / t1 / 1e6, 3),
+            "host_cpu": host_cpu()}
 
 
 def run_form(torch, params, xyz, q, steps, warmup):

@@ -31,6 +31,11 @@ def build(force=True):
     return _LIB
 
 
+def set_threads(n):
+    """Number of OpenMP threads the oracle uses from now on (for timing it)."""
+    _load().omp_set_num_threads(int(n))
+
+
 class _Params(ctypes.Structure):
     _fields_ = [
         ("ni", ctypes.c_int), ("nj", ctypes.c_int), ("nk", ctypes.c_int),
