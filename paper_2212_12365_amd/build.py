@@ -15,9 +15,12 @@ SOURCES = ["lesmi.hip", "les_stage.hip", "les_batch.hip", "les_mlp.hip"]
 HEADERS = ["les_device.h", "les_common.h", "les_stage.h", "les_bcdt.h", "les_mlp.h"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
+# -amdgpu-mfma-vgpr-form: MFMA results go to ordinary VGPRs rather than AGPRs, which saves
+# the accumulator-to-VGPR moves in the closure's inference kernel (the only MFMA code).
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
-         "-Wno-unused-command-line-argument", "-ffp-contract=off", "-Wl,-z,defs"]
+         "-Wno-unused-command-line-argument", "-ffp-contract=off", "-Wl,-z,defs",
+         "-mllvm", "-amdgpu-mfma-vgpr-form=1"]
 
 
 def build(verbose=False):
