@@ -37,8 +37,11 @@ def case(name):
         p = sy.box_params((37, 22, 9), sh, re_acoustic=150.0, cs=0.18)
         return p, xyz, smooth_field(xyz, p.gamma, seed=7)
     if name.startswith("jet"):
+        # jet_mesh6 and jet_mesh10: meshes 6 and 10 of the paper's mesh table (a thin
+        # azimuthal direction, and the table's smallest mesh).
         shapes = {"jet_small": (64, 48, 32), "jet_ragged": (37, 21, 12),
-                  "jet_c2": (256, 128, 128)}
+                  "jet_c2": (256, 128, 128), "jet_mesh6": (400, 150, 10),
+                  "jet_mesh10": (200, 75, 20)}
         n = shapes[name]
         xyz, _ = jet_grid(n)
         p = sy.jet_params(n)

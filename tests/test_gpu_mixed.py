@@ -29,7 +29,8 @@ def _mixed(p, xyz):
     return Context(p.replace(precision=1), xyz)
 
 
-@pytest.mark.parametrize("name", ["skew24", "skew_odd", "jet_ragged", "jet_small", "tgv32"])
+@pytest.mark.parametrize("name", ["skew24", "skew_odd", "jet_ragged", "jet_small", "jet_mesh6",
+                                  "jet_mesh10", "tgv32"])
 def test_mixed_residual(torch, name):
     print(f"[gpu] mixed residual {name}", flush=True)
     p, xyz, q = case(name)

@@ -32,7 +32,8 @@ def _announce(what):
     print(f"[gpu] {what}", flush=True)
 
 
-CASES = ["box4", "tgv32", "skew24", "skew_odd", "jet_ragged", "jet_small"]
+CASES = ["box4", "tgv32", "skew24", "skew_odd", "jet_ragged", "jet_small", "jet_mesh6",
+         "jet_mesh10"]
 
 
 @pytest.mark.parametrize("name", CASES)
@@ -64,8 +65,13 @@ def test_residual(torch, name):
     got = got.cpu().numpy()
     err = rel_l2(got, ref)
     assert np.all(err <= TOL), err
-    # Boundary nodes carry zeros on both sides.
-    assert np.array_equal(got == 0.0, ref == 0.0) or p.bc[0] == 0
+    # Nodes that are not updated (the jet's boundary planes) carry zeros on both sides.
+    # (Interior nodes of a uniform free stream cancel to zero or to a subnormal value
+    # depending on the order of operations, so they are held to the L2 bar only.)
+    if p.bc[0] != 0:
+        fixed = np.ones(got.shape[1:], dtype=bool)
+        fixed[:, 1:-1, 1:-1] = False
+        assert np.all(got[:, fixed] == 0.0) and np.all(ref[:, fixed] == 0.0)
     ctx.close()
 
 
@@ -100,7 +106,8 @@ def test_apply_bc(torch, name):
 
 
 @pytest.mark.parametrize("name,nsteps", [("tgv32", 20), ("skew24", 5), ("jet_small", 5),
-                                         ("jet_ragged", 8), ("skew_odd", 6)])
+                                         ("jet_ragged", 8), ("skew_odd", 6),
+                                         ("jet_mesh10", 3)])
 def test_step(torch, name, nsteps):
     _announce(f"step {name} x{nsteps}")
     p, xyz, q = case(name)
