@@ -171,7 +171,10 @@ __device__ __forceinline__ void bc_node(const Dims& D, const Phys& P, const BcDa
   for (int c = 0; c < 5; ++c) q[(long long)c * N + id] = qo[c];
 }
 
-
+// ---------------------------------------------------------------------------------------
+// Time step (paper, Time Marching Method): dt = CFL min over updated nodes of
+// J^-1 / sum_d Lam_d. The node kernel of a step's first stage writes per-block minima.
+// ---------------------------------------------------------------------------------------
 // dt = CFL times the minimum of the block minima (exact in any order).
 __device__ __forceinline__ void dt_final_block(const double* __restrict__ part, int nparts,
                                                double cfl, double* __restrict__ dt,
