@@ -179,9 +179,9 @@ int les_profile(les_ctx* ctx, int enable);
 int les_profile_read(les_ctx* ctx, double* nodes_ms, double* faces_ms, long long* stages);
 
 /* Autotuner of a single context: times every stage-kernel tile shape with z-chunk depths
- * 4, 8 and 16 on residual evaluations of q (DEVICE [5][N], not modified) and keeps the
- * fastest (les_set_tuning). tile and kmin (HOST, may be NULL) receive the choice.
- * Synchronises the stream. */
+ * 4, 8 and 16 on Runge-Kutta stage updates of q (DEVICE [5][N], read, not modified) with
+ * dt = 0 into the context's stage buffer, and keeps the fastest (les_set_tuning). tile and
+ * kmin (HOST, may be NULL) receive the choice. Synchronises the stream. */
 int les_autotune(les_ctx* ctx, const double* q, int* tile, int* kmin, void* stream);
 
 void les_destroy(les_ctx* ctx);

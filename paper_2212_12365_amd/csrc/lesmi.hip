@@ -845,13 +845,20 @@ int les_autotune(les_ctx* c, const double* q, int* tile, int* kmin, void* stream
   if (!c || !q) return fail(c, LES_EINVAL, "null argument");
   hipStream_t s = (hipStream_t)stream;
   static const int kmins[] = {4, 8, 16};
+  // The candidates run the stage kernel as a step does (the Runge-Kutta update), with
+  // dt = 0 and the output in the context's stage buffer qa: q is read, not modified.
   StageArgs A = stage_args(c, q);
-  A.mode = 0;
+  A.mode = 1;
   A.out = c->qa;
+  A.q0 = q;
+  A.dt = c->d_dt;
+  A.alpha = 0.25;
+  hipLaunchKernelGGL(k_set_scalar, dim3(1), dim3(1), 0, s, c->d_dt, 0.0);
   hipEvent_t e0, e1;
   HIP_TRY(c, hipEventCreate(&e0));
   HIP_TRY(c, hipEventCreate(&e1));
-  hipError_t err = launch_nodes(A, s);
+  hipError_t err = hipGetLastError();
+  if (err == hipSuccess) err = launch_nodes(A, s);
   float best = INFINITY;
   int bt = c->tile, bk = c->kmin;
   for (int t = 0; err == hipSuccess && t < kNumTiles; ++t)
