@@ -81,11 +81,13 @@ def cpu_baseline(params, xyz, q, steps):
     o.step(q, 1, cfl=0.5)
     t1 = time.perf_counter() - t1
     oracle.set_threads(threads)
-    upd = (params.ni - 2) * (params.nj - 2) * params.nk
+    box = params.bc[0] == 0  # a periodic box updates every node; the jet its interior
+    upd = params.ni * params.nj * params.nk if box else (params.ni - 2) * (params.nj - 2) * params.nk
+    kind = "box" if box else "jet"
     return {"value": round(upd * 5 * steps / t / 1e6, 3), "unit": "Mcell-RKstage/s",
             "cores": threads, "kind": "oracle",
             "sample": f"{steps} RK steps (= {5 * steps} stages, with time-step reduction and "
-                      f"boundary conditions) of the same jet {params.ni}x{params.nj}x{params.nk} "
+                      f"boundary conditions) of the same {kind} {params.ni}x{params.nj}x{params.nk} "
                       f"FP64 workload, {t:.1f} s on {threads} OpenMP threads; then 1 step on "
                       f"1 thread, {t1:.1f} s",
             "single_thread_value": round(upd * 5 / t1 / 1e6, 3),
@@ -260,6 +262,9 @@ def main():
                     help="RK steps of the oracle timed for the CPU baseline (0 = skip)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a 1 GiB device copy (counter calibration) and exit")
+    ap.add_argument("--oracle-configs", action="store_true",
+                    help="only time the CPU oracle on the Taylor-Green box (20 steps) and the "
+                         "384x192x192 jet (2 steps) and print one JSON line, then exit")
     ap.add_argument("--mesh-sweep", action="store_true",
                     help="only time the FP64 and mixed forms of the jet on the paper's ten "
                          "meshes (its mesh table) and print one JSON line, then exit")
@@ -273,6 +278,18 @@ def main():
         print(json.dumps({"error": "this build runs the whole grid on one GPU; multi-GPU runs "
                                    "(--gpus > 1) are not supported"}), flush=True)
         sys.exit(2)
+
+    if args.oracle_configs:
+        import synthetic as sy
+        rows = []
+        for name, grid, steps in (("tgv", 32, 20), ("jet", (384, 192, 192), 2)):
+            p, xyz, q = sy.make_case(name, grid, seed=0)
+            r = cpu_baseline(p, xyz, q, steps)
+            r["workload"] = f"{name} {grid}"
+            print(json.dumps(r), file=sys.stderr, flush=True)
+            rows.append(r)
+        print(json.dumps({"oracle_configs": rows}), flush=True)
+        return
 
     import torch
     if args.copy_calibration:
