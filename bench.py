@@ -117,11 +117,12 @@ def run_form(torch, params, xyz, q, steps, warmup):
             "stages": stages, "rate": upd * 5 * steps / wall / 1e6}
 
 
-def mesh_sweep(torch, steps, warmup):
-    """FP64 and mixed-form throughput of the synthetic jet on each of the paper's meshes."""
+def mesh_sweep(torch, steps, warmup, grids=None):
+    """FP64 and mixed-form throughput of the synthetic jet on each of the paper's meshes
+    (or on the given grids)."""
     import synthetic as sy
     rows = []
-    for m, n in enumerate(PAPER_MESHES, 1):
+    for m, n in enumerate(grids or PAPER_MESHES, 1):
         p, xyz, q = sy.make_case("jet", n, seed=0)
         f64 = run_form(torch, p, xyz, q, steps, warmup)
         mx = run_form(torch, p.replace(precision=1), xyz, q, steps, warmup)
@@ -268,6 +269,9 @@ def main():
     ap.add_argument("--mesh-sweep", action="store_true",
                     help="only time the FP64 and mixed forms of the jet on the paper's ten "
                          "meshes (its mesh table) and print one JSON line, then exit")
+    ap.add_argument("--sweep-grids", default="",
+                    help="with --mesh-sweep: grids to time instead of the paper's meshes, "
+                         "e.g. 768x384x384,384x192x192")
     ap.add_argument("--mixed-only", action="store_true",
                     help="only time the mixed-precision form of the jet workload and print its "
                          "figures (for counter runs of its kernels), then exit")
@@ -299,7 +303,8 @@ def main():
     import synthetic as sy
 
     if args.mesh_sweep:
-        rows = mesh_sweep(torch, args.steps, args.warmup)
+        grids = [tuple(int(x) for x in g.split("x")) for g in args.sweep_grids.split(",") if g]
+        rows = mesh_sweep(torch, args.steps, args.warmup, grids or None)
         print(json.dumps({"mesh_sweep": rows, "unit": "Mcell-RKstage/s", "steps": args.steps,
                           "warmup": args.warmup, "workload": "synthetic jet, CFL 0.5, Smagorinsky"}),
               flush=True)
