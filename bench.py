@@ -279,7 +279,7 @@ def main():
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print(json.dumps({"error": "this build runs the whole grid on one GPU; multi-GPU runs "
+        print(json.dumps({"error": "this library runs the whole grid on one GPU; multi-GPU runs "
                                    "(--gpus > 1) are not supported"}), flush=True)
         sys.exit(2)
 

@@ -1,5 +1,5 @@
-"""Long-run checks of the full workloads (minutes; not collected by pytest). Run on a GPU machine
-from the repository root:
+"""Long-run checks of the full workloads (minutes; not collected by pytest). Run on a machine
+with an MI355X, from the repository root:
 
     python tests/long_runs.py [--steps 500]
 
