@@ -77,10 +77,17 @@ typedef struct {
   float lo[LES_MLP_INPUTS], hi[LES_MLP_INPUTS];         /* trained input range */
 } les_mlp_norm;
 
+/* Largest grid, ni * nj * nk nodes: the kernels address planes of per-node arrays with 32-bit
+ * offsets (at most 11 planes of N values), so N must satisfy 11 N <= 2^31 - 1. That is
+ * 195,225,786 nodes, about 58 GB of FP64 state and metrics; les_init_grid rejects larger
+ * grids with LES_EINVAL before touching the device. */
+#define LES_MAX_NODES 195225786LL
+
 /* Problem parameters (paper: Dimensionless Formulation, LES formulation, Subgrid Scale
  * Modeling, Spatial Discretization, Boundary Conditions). Supported boundary sets:
  * all six faces periodic (a box), or the jet set {i-: JET_INFLOW, i+: EXIT, j-: AXIS,
- * j+: FARFIELD, k: PERIODIC}. Each direction needs at least 4 nodes. */
+ * j+: FARFIELD, k: PERIODIC}. Each direction needs at least 4 nodes, and the grid at most
+ * LES_MAX_NODES nodes. */
 typedef struct {
   int ni, nj, nk;
   int bc[6];                  /* faces i-, i+, j-, j+, k-, k+ (les_bc) */
@@ -103,7 +110,8 @@ typedef struct {
  * S_d = J^-1 grad(xi_d) in conservative form and J^-1 = det(dx/dxi) from the node
  * coordinates, and the boundary normals. `xyz` is a HOST array [3][nk][nj][ni] (x, y, z).
  * Synchronous. Returns LES_EGRID if J^-1 <= 0 at an updated node (the context is still
- * created so the caller may inspect it), LES_EINVAL for unsupported parameters. */
+ * created so the caller may inspect it), LES_EINVAL for unsupported parameters or a grid of
+ * more than LES_MAX_NODES nodes (checked before any device call; *out stays NULL). */
 int les_init_grid(const les_params* params, const double* xyz, les_ctx** out);
 
 /* Residual RHS_ijk of the semi-discrete system dQ/dt = -J RHS (paper, Spatial
@@ -151,6 +159,15 @@ int les_residual_norms(les_ctx* ctx, const double* q, double* out, void* stream)
 int les_stats_reset(les_ctx* ctx);
 int les_stats_accumulate(les_ctx* ctx, const double* q, void* stream);
 int les_stats_read(les_ctx* ctx, double* mean, double* rms, long long* samples, void* stream);
+
+/* Azimuthal reduction of the running statistics, the products the paper's Numerical Results
+ * need from a converged run of the round jet: out DEVICE [2][5][nj][ni]; out[0][c][j][i] is
+ * the mean over the azimuthal index k (summed in increasing k, divided by nk) of the time
+ * mean of component c of (rho, u, v, w, p) at (i, j, k), out[1][c][j][i] the same of the
+ * r.m.s. fluctuation. The centreline decay is out[0][1][0][i] over the axial stations i; a
+ * radial profile at station i is out[.][c][j][i] over j. Needs at least one sample
+ * (LES_ESTATE otherwise). */
+int les_stats_azimuthal(les_ctx* ctx, double* out, void* stream);
 
 /* Copies the context's metrics to DEVICE arrays S [9][N] (S_d^c at index 3d + c) and
  * jinv [N]; either may be NULL. */

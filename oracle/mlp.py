@@ -181,3 +181,46 @@ def target(sig, grad, rho, jinv):
     with np.errstate(divide="ignore", invalid="ignore"):
         c = np.where((den > 0) & (jinv > 0), num / den, 0.0)
     return np.maximum(c, 0.0)
+
+
+def closure_step(o, theta, norm, cs2, q, nsteps, cfl=0.5, dt_fixed=0.0):
+    """Runge-Kutta steps of the oracle `o` (an oracle.Oracle) with the learned closure, as
+    the oracle's own step takes them with Smagorinsky (paper, Time Marching Method: the
+    five stages with alpha = 1/4, 1/6, 3/8, 1/2, 1 and the boundary conditions after every
+    stage; dt = CFL min J^-1 / sum of the spectral radii from the state at the start of the
+    step), except that at every stage the eddy viscosity is mu_t = rho c Delta^2 |S|, with
+    c from the FP64 network on that stage's velocity gradient (`coefficient`, with the
+    fallback to cs2) and Delta^3 = J^-1.
+
+    norm: (mean, inv_std, lo, hi) arrays. Returns (q, dt of the last step)."""
+    alpha = (0.25, 1.0 / 6.0, 0.375, 0.5, 1.0)
+    p = o.p
+    shape = p.shape
+    per = (p.bc[0] == 0, p.bc[2] == 0, p.bc[4] == 0)
+    upd = np.ones(shape, dtype=bool)
+    for d, ax in ((0, 2), (1, 1), (2, 0)):
+        if not per[d]:
+            sl = [slice(None)] * 3
+            sl[ax] = 0
+            upd[tuple(sl)] = False
+            sl[ax] = shape[ax] - 1
+            upd[tuple(sl)] = False
+    jinv = o.jinv
+    J = np.where(upd, 1.0 / np.where(upd, jinv, 1.0), 0.0)
+    delta2 = np.cbrt(np.maximum(jinv, 0.0)) ** 2
+    mean, inv_std, lo, hi = norm
+    q = np.array(q, dtype=np.float64, copy=True)
+    dt = dt_fixed
+    for _ in range(nsteps):
+        if cfl > 0.0:
+            dt = o.dt(q, cfl)
+        q0 = q.copy()
+        for a in alpha:
+            f, smag = invariants(o.velocity_gradient(q))
+            c, _ = coefficient(theta, mean, inv_std, lo, hi, f.reshape(6, -1), smag.reshape(-1),
+                               cs2)
+            mut = q[0] * c.reshape(shape) * delta2 * smag
+            rhs = o.residual_with_mut(q, mut)
+            q = np.where(upd[None], q0 - a * dt * J[None] * rhs, q)
+            q = o.apply_bc(q)
+    return q, dt

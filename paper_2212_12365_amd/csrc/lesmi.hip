@@ -21,6 +21,9 @@ namespace {
 
 constexpr int kBlock = 256;
 constexpr int kMaxPartials = 4096;
+// Largest grid: every plane offset c * N + o of an array of kRecCount planes fits in an int.
+constexpr long long kMaxNodes = 2147483647LL / kRecCount;
+static_assert(kMaxNodes == LES_MAX_NODES, "header limit");
 
 inline unsigned grid_for(long long n, int block = kBlock) {
   return (unsigned)((n + block - 1) / block);
@@ -278,6 +281,27 @@ __global__ void k_stats_read(long long n, const double* __restrict__ sum,
   if (rms) rms[id] = sqrt(fmax(sq[id] / count - m * m, 0.0));
 }
 
+// Azimuthal averages of the statistics: one thread per (c, j, i) sums the time mean and the
+// r.m.s. fluctuation of component c over k = 0 .. nk-1 in increasing k, then divides by nk.
+// out [2][5][nj][ni]: out[0] the averaged mean, out[1] the averaged r.m.s.
+__global__ void k_stats_azimuthal(Dims D, const double* __restrict__ sum,
+                                  const double* __restrict__ sq, double count,
+                                  double* __restrict__ out) {
+  const long long plane = (long long)D.n[0] * D.n[1];
+  const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= 5 * plane) return;
+  const long long c = t / plane, ij = t % plane;
+  double am = 0.0, ar = 0.0;
+  for (int k = 0; k < D.n[2]; ++k) {
+    const long long id = c * D.N + ij + plane * k;
+    const double m = sum[id] / count;
+    am += m;
+    ar += sqrt(fmax(sq[id] / count - m * m, 0.0));
+  }
+  out[c * plane + ij] = am / D.n[2];
+  out[5 * plane + c * plane + ij] = ar / D.n[2];
+}
+
 // Sum of squares and largest magnitude of the mass residual over updated nodes, per fixed
 // node range; then one fixed-order pass.
 __global__ void k_rhs_norm_partial(Dims D, const double* __restrict__ rhs,
@@ -368,6 +392,9 @@ int validate(const les_params* p, Dims* D) {
   if (p->closure != LES_SMAGORINSKY && p->closure != LES_MLP) return LES_EINVAL;
   D->jet = jet ? 1 : 0;
   D->N = (long long)n[0] * n[1] * n[2];
+  // The kernels index a plane c of an array [planes][N] with 32-bit offsets c*N + o; the
+  // largest such array holds kRecCount planes (the node records).
+  if (D->N > kMaxNodes) return LES_EINVAL;
   return LES_OK;
 }
 
@@ -750,6 +777,15 @@ int les_stats_read(les_ctx* c, double* mean, double* rms, long long* samples, vo
   hipLaunchKernelGGL(k_stats_read, dim3(grid_for(n)), dim3(kBlock), 0, (hipStream_t)stream, n,
                      c->stat_sum, c->stat_sq, (double)c->stat_n, mean, rms);
   if (samples) *samples = c->stat_n;
+  return launch_check(c, "statistics");
+}
+
+int les_stats_azimuthal(les_ctx* c, double* out, void* stream) {
+  if (!c || !out) return fail(c, LES_EINVAL, "null argument");
+  if (!c->stat_sum || c->stat_n == 0) return fail(c, LES_ESTATE, "no statistics sample");
+  const long long n = 5LL * c->dims.n[0] * c->dims.n[1];
+  hipLaunchKernelGGL(k_stats_azimuthal, dim3(grid_for(n)), dim3(kBlock), 0, (hipStream_t)stream,
+                     c->dims, c->stat_sum, c->stat_sq, (double)c->stat_n, out);
   return launch_check(c, "statistics");
 }
 

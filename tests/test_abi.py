@@ -36,3 +36,25 @@ def test_params_struct_layout_matches_header():
         count = getattr(ctype, "_length_", 1)
         ours.append((name, base, count))
     assert declared == ours
+
+
+def test_oversized_grid_is_rejected_before_any_device_call():
+    """Grids whose per-node planes would overflow the kernels' 32-bit offsets are refused by
+    les_init_grid's parameter check, which runs before any HIP call (no GPU here)."""
+    import numpy as np
+    import synthetic as sy
+    lib = lesmi.load()
+    text = open(lesmi.HEADER).read()
+    limit = int(re.search(r"#define LES_MAX_NODES (\d+)LL", text).group(1))
+    assert limit == (2 ** 31 - 1) // 11
+    dummy = np.zeros(3)
+    for n in [(581, 581, 579), (1200, 600, 300), (4096, 4096, 16)]:
+        assert n[0] * n[1] * n[2] > limit
+        for p in (sy.jet_params(n), sy.box_params(n, np.zeros((3, 3)))):
+            s = lesmi.make_params(p)
+            h = ctypes.c_void_p(1)
+            rc = lib.les_init_grid(ctypes.byref(s),
+                                   dummy.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                   ctypes.byref(h))
+            assert rc == lesmi.LES_EINVAL
+            assert not h.value

@@ -144,3 +144,31 @@ def test_filter_target_linear_field():
     assert np.allclose(c[1:-1, 1:-1, 1:-1], 1 / (32 * math.sqrt(12)), rtol=1e-10)
     c = mlp.target(sig, -grad, qb[0], o.jinv)  # the opposite strain projects negative: 0
     assert np.all(c[1:-1, 1:-1, 1:-1] == 0.0)
+
+
+def test_closure_step_with_constant_network_is_the_smagorinsky_step():
+    """The learned-closure step (Python stages around the C oracle's residual) with a network
+    whose output is the constant C_s^2 (zero output weights, b3 = softplus^-1(C_s^2)) must be
+    the C oracle's own Smagorinsky Runge-Kutta step: two independent implementations of the
+    stage loop, the time step and the boundary conditions."""
+    from synthetic.grids import jet_grid
+    n = (20, 12, 8)
+    xyz, _ = jet_grid(n)
+    p = sy.jet_params(n)
+    q = sy.jet_field(xyz, gamma=p.gamma, mach_jet=p.mach_jet, u_inf=p.u_inf[0], seed=2)
+    o = oracle.Oracle(p, xyz)
+    q = o.apply_bc(q)
+    cs2 = p.cs ** 2
+    th = np.zeros(mlp.NPARAMS)
+    th[mlp.OFF_B3] = math.log(math.expm1(cs2))
+    norm = (np.zeros(6), np.ones(6), np.full(6, -np.inf), np.full(6, np.inf))
+    got, dt = mlp.closure_step(o, th, norm, cs2, q, 3, cfl=0.5)
+    ref, dtref = o.step(q, 3, cfl=0.5)
+    assert dt == pytest.approx(dtref, rel=1e-15)
+    err = np.abs(got - ref).reshape(5, -1).max(1) / np.abs(ref).reshape(5, -1).max(1)
+    assert np.all(err <= 1e-13), err
+    # and the closure acts: with c = 0 the state differs
+    th0 = th.copy()
+    th0[mlp.OFF_B3] = -50.0
+    off, _ = mlp.closure_step(o, th0, norm, cs2, q, 3, cfl=0.5)
+    assert np.abs(off - ref).max() > 1e3 * np.abs(got - ref).max()
