@@ -149,11 +149,12 @@ def aposteriori(fine, coarse, xyzc, q_fine, q_start, theta, norm, fine_steps, sm
 
 
 def run(fine_shape=(768, 384, 384), spinup=1200, every=200, count=3, steps=600, batch=8192,
-        lr=2e-3, seed=0, smin=1.0, post_steps=400, log=print):
+        lr=2e-3, seed=0, smin=1.0, post_steps=400, log=print, return_network=False):
     """End-to-end training of the closure on the jet: an FP64 run on the fine grid (seeded
     jet field), `count` snapshots box-filtered onto the grid of half the nodes per direction,
     training on all but the last snapshot and evaluation on the last; then, if post_steps > 0,
-    the a-posteriori comparison over post_steps fine steps. Returns a dict."""
+    the a-posteriori comparison over post_steps fine steps. Returns a dict (with the trained
+    network under "theta" and "norm" if return_network)."""
     import time as _time
     import torch
     import synthetic as sy
@@ -202,6 +203,8 @@ def run(fine_shape=(768, 384, 384), spinup=1200, every=200, count=3, steps=600, 
                                          post_steps, smin, log)
     fine.close()
     coarse.close()
+    if return_network:
+        res["theta"], res["norm"] = theta, norm
     return res
 
 

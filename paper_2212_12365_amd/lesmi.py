@@ -124,6 +124,7 @@ def load():
         lib.les_stats_reset.argtypes = [vp]
         lib.les_stats_accumulate.argtypes = [vp, vp, vp]
         lib.les_stats_read.argtypes = [vp, vp, vp, ctypes.POINTER(ctypes.c_longlong), vp]
+        lib.les_stats_azimuthal.argtypes = [vp, vp, vp]
         lib.les_destroy.argtypes = [vp]
         lib.les_destroy.restype = None
         lib.les_last_error.argtypes = [vp]
@@ -278,6 +279,16 @@ class Context:
                                             _dev(rms, 5 * self.n, "rms"), ctypes.byref(n),
                                             _stream(stream)), "les_stats_read")
         return mean, rms, n.value
+
+    def stats_azimuthal(self, stream=None):
+        """Azimuthal averages of the time mean and r.m.s. of (rho, u, v, w, p): a tensor
+        [2][5][nj][ni] (les_stats_azimuthal)."""
+        import torch
+        nk, nj, ni = self.shape
+        out = torch.empty((2, 5, nj, ni), dtype=torch.float64, device="cuda")
+        self._check(self.lib.les_stats_azimuthal(self.handle, _dev(out, 10 * nj * ni, "out"),
+                                                 _stream(stream)), "les_stats_azimuthal")
+        return out
 
     def metrics(self, stream=None):
         import torch

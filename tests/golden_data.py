@@ -19,3 +19,17 @@ def paper_constants():
             vals = [float(Fraction(v)) for v in value]
             out[name.strip()] = vals if len(vals) > 1 else vals[0]
     return out
+
+
+def named_rows(fname):
+    """name -> numpy array of the values of a `name v1 v2 ...` fixture (comments skipped)."""
+    import numpy as np
+    out = {}
+    with open(os.path.join(GOLDEN, fname)) as f:
+        for line in f:
+            line = line.strip()
+            if not line or line.startswith("#"):
+                continue
+            name, *vals = line.split()
+            out[name] = np.array([float(v) for v in vals])
+    return out

@@ -3,8 +3,11 @@
 
 * jet 256 x 128 x 128, FP64: residual and one CFL-0.5 Runge-Kutta step, every element,
   relative L2 <= 1e-12 per component.
-* the same grid in the mixed form: residual <= 2e-5.
-* jet 384 x 192 x 192 in the mixed form: the state increment of one step <= 2e-5.
+* the same grid in the mixed form: residual <= 2e-5 in relative L2 per component, and the
+  largest error of each component over the updated nodes <= 1e-5 of its flux scale (see
+  test_gpu_mixed).
+* jet 384 x 192 x 192 in the mixed form: the state increment of one step <= 2e-5, and the
+  mixed run against the FP64 run over 100 steps (rho, u, E) <= 2e-5.
 * every stage-kernel tile variant gives bitwise the same residual (the same arithmetic runs
   in the same order for each face and node whatever the launch shape).
 """
@@ -63,9 +66,13 @@ def test_c2_mixed_residual(torch, c2):
     p, xyz, q, o = c2
     ctx = Context(p.replace(precision=1), xyz)
     got = ctx.residual(torch.from_numpy(q).cuda()).cpu().numpy()
-    err = rel_l2(got, o.residual(q))
-    print("C2 mixed residual rel-L2", err)
+    ref = o.residual(q)
+    err = rel_l2(got, ref)
+    from test_gpu_mixed import LINF_TOL, flux_scale, updated_mask
+    linf = np.abs(got - ref)[:, updated_mask(p)].max(axis=1) / flux_scale(o, q, p.gamma)
+    print("C2 mixed residual rel-L2", err, "Linf / flux scale", linf)
     assert np.all(err <= 2e-5), err
+    assert np.all(linf <= LINF_TOL), linf
     ctx.close()
 
 
@@ -85,6 +92,35 @@ def test_c3_mixed_step(torch):
     print("C3 mixed one-step increment rel-L2", err)
     assert np.all(err <= 2e-5), err
     ctx.close()
+
+
+def test_c3_mixed_vs_fp64_100_steps(torch):
+    """The mixed form stepped beside the FP64 form on the GPU from the same state for 100
+    steps of the 384 x 192 x 192 jet; relative L2 and L-infinity of rho, u and E every 25
+    steps, each <= 2e-5 (the mixed form's bar)."""
+    _announce("jet 384x192x192 mixed vs fp64, 100 steps")
+    from paper_2212_12365_amd.lesmi import Context
+    p, xyz, q = sy.make_case("jet", (384, 192, 192), seed=0)
+    c64 = Context(p, xyz)
+    c32 = Context(p.replace(precision=1), xyz)
+    g64 = torch.from_numpy(q).cuda()
+    c64.apply_bc(g64)
+    g32 = g64.clone()
+
+    def rel(a, b):
+        return (float(torch.linalg.vector_norm(a - b) / torch.linalg.vector_norm(b)),
+                float((a - b).abs().max() / b.abs().max()))
+
+    for n in range(25, 101, 25):
+        c64.step(g64, 25, cfl=0.5)
+        c32.step(g32, 25, cfl=0.5)
+        errs = {"rho": rel(g32[0], g64[0]), "u": rel(g32[1] / g32[0], g64[1] / g64[0]),
+                "E": rel(g32[4], g64[4])}
+        print(f"step {n}: mixed vs fp64 [rel L2, rel Linf] {errs}", flush=True)
+        for k, (l2, linf) in errs.items():
+            assert l2 <= 2e-5 and linf <= 2e-5, (n, k, l2, linf)
+    c64.close()
+    c32.close()
 
 
 @pytest.mark.parametrize("precision", [0, 1])

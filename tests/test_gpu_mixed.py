@@ -1,11 +1,19 @@
 """GPU parity of the mixed-precision form (FP32 flux and stencil arithmetic; FP64 state,
 Runge-Kutta accumulation, J^-1 and time-step reduction) against the FP64 oracle.
 
-Bar: per-component relative L2 <= 2e-5 for the residual and for the state increment of
-a few Runge-Kutta steps, on the jet grids (the mixed-precision workload is a jet) and on a
-skewed periodic box. The Mach 0.1 Taylor-Green box is reported: its mass and energy
-residuals are O(M^2)-small differences of O(M) fluxes, beyond FP32 at 2e-5, so only its
-momentum components are held to the bar."""
+Bars:
+* per-component relative L2 <= 2e-5 for the residual and for the state increment of a few
+  Runge-Kutta steps, on the jet grids (the mixed-precision workload is a jet) and on skewed
+  periodic boxes;
+* per-component L-infinity of the residual error, over the updated nodes, against the
+  component's flux scale F_c = max over nodes and directions of the inviscid node flux
+  |W_c U_d + p S_d,c| (U_d = S_d . u): max |err_c| <= 1e-5 F_c. A residual is a difference of
+  six face fluxes each evaluated in FP32 (unit round-off 6e-8), so its error is bounded by a
+  modest multiple of that round-off times the flux, at every node. This bar holds on every
+  case and component, including the Mach 0.1 Taylor-Green box, whose mass and energy
+  residuals are O(M^2)-small differences of O(M) fluxes: there the relative L2 measures the
+  cancellation, not the arithmetic, and only its momentum components are held to 2e-5 in
+  relative L2 (mass and energy are reported)."""
 import numpy as np
 import pytest
 
@@ -15,6 +23,29 @@ from gpu_cases import case, rel_l2
 pytestmark = pytest.mark.gpu
 
 TOL = 2e-5
+LINF_TOL = 1e-5
+
+
+def flux_scale(o, q, gamma):
+    """F_c = max over nodes and directions of |W_c U_d + p S_d,c| (the inviscid node flux)."""
+    x = oracle.primitives(q, gamma)
+    u, v, w, pr = x[1], x[2], x[3], x[4]
+    F = np.zeros(5)
+    for d in range(3):
+        sx, sy, sz = o.S[3 * d], o.S[3 * d + 1], o.S[3 * d + 2]
+        U = sx * u + sy * v + sz * w
+        comps = [q[0] * U, q[1] * U + pr * sx, q[2] * U + pr * sy, q[3] * U + pr * sz,
+                 (q[4] + pr) * U]
+        F = np.maximum(F, [np.abs(c).max() for c in comps])
+    return F
+
+
+def updated_mask(p):
+    m = np.ones(p.shape, dtype=bool)
+    if p.bc[0] != 0:
+        m[:, :, 0] = m[:, :, -1] = False
+        m[:, 0, :] = m[:, -1, :] = False
+    return m
 
 
 @pytest.fixture(scope="module")
@@ -41,9 +72,12 @@ def test_mixed_residual(torch, name):
     ctx = _mixed(p, xyz)
     got = ctx.residual(torch.from_numpy(q).cuda()).cpu().numpy()
     err = rel_l2(got, ref)
-    print(f"mixed residual rel-L2 {name}: {err}")
+    upd = updated_mask(p)
+    linf = np.abs(got - ref)[:, upd].max(axis=1) / flux_scale(o, q, p.gamma)
+    print(f"mixed residual rel-L2 {name}: {err}; Linf / flux scale: {linf}")
     comps = [1, 2, 3] if name == "tgv32" else range(5)
     assert all(err[c] <= TOL for c in comps), err
+    assert np.all(linf <= LINF_TOL), linf
     ctx.close()
 
 
