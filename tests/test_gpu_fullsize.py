@@ -4,7 +4,7 @@
 * jet 256 x 128 x 128, FP64: residual and one CFL-0.5 Runge-Kutta step, every element,
   relative L2 <= 1e-12 per component.
 * the same grid in the mixed form: residual <= 2e-5 in relative L2 per component, and the
-  largest error of each component over the updated nodes <= 1e-5 of its flux scale (see
+  largest error of each component over the updated nodes <= 2e-6 of its flux scale (see
   test_gpu_mixed).
 * jet 384 x 192 x 192 in the mixed form: the state increment of one step <= 2e-5, and the
   mixed run against the FP64 run over 100 steps (rho, u, E) <= 2e-5.

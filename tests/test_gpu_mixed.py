@@ -7,9 +7,10 @@ Bars:
   periodic boxes;
 * per-component L-infinity of the residual error, over the updated nodes, against the
   component's flux scale F_c = max over nodes and directions of the inviscid node flux
-  |W_c U_d + p S_d,c| (U_d = S_d . u): max |err_c| <= 1e-5 F_c. A residual is a difference of
+  |W_c U_d + p S_d,c| (U_d = S_d . u): max |err_c| <= 2e-6 F_c. A residual is a difference of
   six face fluxes each evaluated in FP32 (unit round-off 6e-8), so its error is bounded by a
-  modest multiple of that round-off times the flux, at every node. This bar holds on every
+  modest multiple of that round-off times the flux, at every node (measured at most 3.3e-7 F_c,
+  on the Taylor-Green box's energy residual). This bar holds on every
   case and component, including the Mach 0.1 Taylor-Green box, whose mass and energy
   residuals are O(M^2)-small differences of O(M) fluxes: there the relative L2 measures the
   cancellation, not the arithmetic, and only its momentum components are held to 2e-5 in
@@ -23,7 +24,7 @@ from gpu_cases import case, rel_l2
 pytestmark = pytest.mark.gpu
 
 TOL = 2e-5
-LINF_TOL = 1e-5
+LINF_TOL = 2e-6
 
 
 def flux_scale(o, q, gamma):
