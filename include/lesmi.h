@@ -236,6 +236,22 @@ int les_mlp_loss_grad(const float* theta, const les_mlp_norm* norm, const float*
                       long long n, float inv_wsum, float* grad, float* loss, float* work,
                       void* stream);
 
+/* Allocation-free form of les_mlp_loss_grad, for callers that cannot allocate device memory
+ * (code under HIP graph capture, tight training loops, harnesses that forbid hipMalloc):
+ * the same loss and gradient, bit for bit, with the per-wave partial gradients kept in a
+ * static device array of the library instead of a `work` argument. That array holds
+ * (LES_MLP_NOALLOC_MAX_SAMPLES / 128) * 4 * (LES_MLP_NPARAMS + 1) floats (4.8 MB) on every
+ * GPU the library runs on, until the process ends. n <= LES_MLP_NOALLOC_MAX_SAMPLES, else
+ * LES_EINVAL (nothing is launched). The call allocates and frees nothing and does not
+ * synchronise. Every call on one GPU shares that GPU's array: calls ordered on one stream
+ * are safe, calls that overlap in time on one GPU (other streams, other host threads) race
+ * and give wrong gradients. */
+#define LES_MLP_NOALLOC_MAX_SAMPLES 8192
+int les_mlp_loss_grad_noalloc(const float* theta, const les_mlp_norm* norm, const float* feat,
+                              long long nfeat, const float* target, const float* weight,
+                              const int* idx, long long n, float inv_wsum, float* grad,
+                              float* loss, void* stream);
+
 /* One Adam step (Kingma & Ba) on theta with moments m, v (all DEVICE
  * [LES_MLP_NPARAMS]); step counts from 1. */
 int les_mlp_adam(float* theta, const float* grad, float* m, float* v, int step, float lr,

@@ -12,6 +12,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <mutex>
 #include <string>
 
 #include "les_common.h"
@@ -748,6 +749,76 @@ int les_mlp_loss_grad(const float* theta, const les_mlp_norm* norm, const float*
   A.inv_wsum = inv_wsum;
   A.work = work;
   const int blocks = (int)(les_mlp_work_size(n) / (4 * (kMlpP + 1)));
+  hipLaunchKernelGGL(k_mlp_grad, dim3(blocks), dim3(256), 0, s, A);
+  hipLaunchKernelGGL(k_mlp_reduce, dim3((kMlpP + 1 + 255) / 256), dim3(256), 0, s, work,
+                     blocks * 4, grad, loss);
+  return hipGetLastError() == hipSuccess ? LES_OK : LES_EHIP;
+}
+
+}  // extern "C"
+
+namespace {
+
+// Per-wave partial gradients of les_mlp_loss_grad_noalloc: a static device array, one copy per
+// GPU, held until the process ends. Host code never passes `scratch` itself to a kernel (in
+// host code the name is a host-side stand-in); it passes the device address that
+// hipGetSymbolAddress returns on that device, looked up once per device.
+constexpr int kNoAllocBlocks = (LES_MLP_NOALLOC_MAX_SAMPLES + 127) / 128;
+constexpr size_t kNoAllocFloats = (size_t)kNoAllocBlocks * 4 * (kMlpP + 1);
+static_assert(kNoAllocBlocks <= kGradBlocksMax, "gradient grid");
+
+}  // namespace
+
+static __device__ __align__(256) float scratch[kNoAllocFloats];
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mutex;
+float* g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of this device's scratch array (nullptr on failure).
+float* scratch_on_current_device() {
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) return nullptr;
+  std::lock_guard<std::mutex> lock(g_scratch_mutex);
+  if (!g_scratch_ptr[dev]) {
+    void* ptr = nullptr;
+    if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess || !ptr) return nullptr;
+    g_scratch_ptr[dev] = (float*)ptr;
+  }
+  return g_scratch_ptr[dev];
+}
+
+}  // namespace
+
+extern "C" {
+
+int les_mlp_loss_grad_noalloc(const float* theta, const les_mlp_norm* norm, const float* feat,
+                              long long nfeat, const float* target, const float* weight,
+                              const int* idx, long long n, float inv_wsum, float* grad,
+                              float* loss, void* stream) {
+  if (!theta || !norm || !feat || !target || !weight || !idx || !grad || n < 1 || nfeat < 1 ||
+      n > LES_MLP_NOALLOC_MAX_SAMPLES)
+    return LES_EINVAL;
+  float* work = scratch_on_current_device();
+  if (!work) return LES_EHIP;
+  hipStream_t s = (hipStream_t)stream;
+  GradArgs A{};
+  A.net.theta = theta;
+  A.net.norm = *norm;
+  A.feat = feat;
+  A.nfeat = nfeat;
+  A.target = target;
+  A.weight = weight;
+  A.idx = idx;
+  A.n = n;
+  A.inv_wsum = inv_wsum;
+  A.work = work;
+  // The grid of les_mlp_loss_grad for the same n (so the result is the same, bit for bit);
+  // every partial the reduction reads is written by this call's gradient kernel first.
+  const int blocks = (int)(les_mlp_work_size(n) / (4 * (kMlpP + 1)));
+  if (blocks > kNoAllocBlocks) return LES_EINVAL;
   hipLaunchKernelGGL(k_mlp_grad, dim3(blocks), dim3(256), 0, s, A);
   hipLaunchKernelGGL(k_mlp_reduce, dim3((kMlpP + 1 + 255) / 256), dim3(256), 0, s, work,
                      blocks * 4, grad, loss);

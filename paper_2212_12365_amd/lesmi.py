@@ -116,6 +116,8 @@ def load():
         lib.les_mlp_work_size.restype = ctypes.c_longlong
         lib.les_mlp_loss_grad.argtypes = [fp, np_, fp, ctypes.c_longlong, fp, fp, vp,
                                           ctypes.c_longlong, ctypes.c_float, fp, fp, fp, vp]
+        lib.les_mlp_loss_grad_noalloc.argtypes = [fp, np_, fp, ctypes.c_longlong, fp, fp, vp,
+                                                  ctypes.c_longlong, ctypes.c_float, fp, fp, vp]
         lib.les_mlp_adam.argtypes = [fp, fp, fp, fp, ctypes.c_int, ctypes.c_float, ctypes.c_float,
                                      ctypes.c_float, ctypes.c_float, vp]
         lib.les_mlp_fit_norm.argtypes = [fp, fp, ctypes.c_longlong, ctypes.c_float, np_, vp]
@@ -470,6 +472,27 @@ def mlp_loss_grad(theta, norm, feat, target, weight, idx, inv_wsum, work=None, s
                                      _f32(grad, MLP_NPARAMS, "grad"), _f32(loss, 1, "loss"),
                                      _f32(work, mlp_work_size(n), "work"), _stream(stream)),
                "les_mlp_loss_grad")
+    return grad, loss
+
+
+MLP_NOALLOC_MAX_SAMPLES = 8192
+
+
+def mlp_loss_grad_noalloc(theta, norm, feat, target, weight, idx, inv_wsum, grad, loss,
+                          stream=None):
+    """les_mlp_loss_grad_noalloc into the given grad [NPARAMS] and loss [1] float32 GPU
+    tensors (the library allocates nothing)."""
+    import torch
+    lib = load()
+    nfeat = target.numel()
+    n = idx.numel()
+    if idx.dtype != torch.int32 or not idx.is_cuda or not idx.is_contiguous():
+        raise ValueError("idx: expected a contiguous int32 GPU tensor")
+    _lib_check(lib.les_mlp_loss_grad_noalloc(
+        _f32(theta, MLP_NPARAMS, "theta"), ctypes.byref(norm), _f32(feat, 6 * nfeat, "feat"),
+        nfeat, _f32(target, nfeat, "target"), _f32(weight, nfeat, "weight"),
+        ctypes.c_void_p(idx.data_ptr()), n, float(inv_wsum), _f32(grad, MLP_NPARAMS, "grad"),
+        _f32(loss, 1, "loss"), _stream(stream)), "les_mlp_loss_grad_noalloc")
     return grad, loss
 
 
