@@ -181,6 +181,13 @@ long long les_updated_nodes(const les_ctx* ctx);
  * z-planes one block marches through. Results do not depend on the choice (the same
  * arithmetic runs in the same order for every node); only the speed does. */
 int les_set_tuning(les_ctx* ctx, int tile, int kmin);
+
+/* enable != 0 (the default): les_step captures one Runge-Kutta step in a HIP graph on the
+ * context's own stream, keeps it, and replays it on the caller's stream (recaptured when the
+ * state pointer, the time-step mode or value, the tuning or the network changes; not used
+ * while les_profile is on). 0: the kernels are launched one by one. The results are the
+ * same either way. */
+int les_set_graph(les_ctx* ctx, int enable);
 int les_tuning_count(void);
 const char* les_tuning_name(int tile);
 

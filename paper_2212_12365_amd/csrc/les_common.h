@@ -95,4 +95,14 @@ struct les_ctx {
   bool prof = false;
   std::vector<hipEvent_t> ev;
   size_t nrec = 0;
+
+  // One Runge-Kutta step captured in a HIP graph (on the context's own non-blocking stream)
+  // and replayed on the caller's stream; recaptured when the state pointer, the time-step
+  // mode or value, the launch tuning or the network normalisation changes.
+  bool use_graph = true;
+  hipStream_t cap = nullptr;
+  hipGraphExec_t exec = nullptr;
+  const double* graph_q = nullptr;
+  double graph_cfl = 0.0, graph_dt = 0.0;
+  int graph_tile = -1, graph_kmin = -1;
 };

@@ -431,8 +431,16 @@ int dev_alloc(les_ctx* c, T** p, size_t count) {
   return LES_OK;
 }
 
+void drop_graph(les_ctx* c) {
+  if (c->exec) (void)hipGraphExecDestroy(c->exec);
+  c->exec = nullptr;
+}
+
 void free_ctx(les_ctx* c) {
   if (!c) return;
+  drop_graph(c);
+  if (c->cap) (void)hipStreamDestroy(c->cap);
+  c->cap = nullptr;
   for (hipEvent_t e : c->ev) (void)hipEventDestroy(e);
   c->ev.clear();
   void* ptrs[] = {c->S, c->jinv, c->jac, c->bc.nff, c->bc.nin, c->bc.nex, c->bc.jetmask,
@@ -548,6 +556,54 @@ int run_bc(les_ctx* c, double* q, hipStream_t s) {
   long long nbc = 2LL * (D.n[0] - 2) * D.n[2] + 2LL * D.n[1] * D.n[2];
   hipLaunchKernelGGL(k_bc, dim3(grid_for(nbc)), dim3(kBlock), 0, s, D, c->phys, c->bc, q);
   return launch_check(c, "boundary kernels");
+}
+
+// One Runge-Kutta step of q on stream s (paper, Time Marching Method): the time step (fixed,
+// or reduced inside the first stage), then five stages, each followed by the boundary
+// conditions. No host synchronisation; no memory set or copy nodes, so it can be captured.
+int enqueue_step(les_ctx* c, double* q, double cfl, double dt_fixed, hipStream_t s) {
+  if (!(cfl > 0.0)) hipLaunchKernelGGL(k_set_scalar, dim3(1), dim3(1), 0, s, c->d_dt, dt_fixed);
+  const double* in = q;
+  for (int l = 0; l < 5; ++l) {
+    double* outb = (l == 4) ? q : ((l % 2 == 0) ? c->qa : c->qb);
+    int rc = run_stage(c, in, 1, outb, q, kAlpha[l], s, (l == 0 && cfl > 0.0) ? cfl : 0.0);
+    if (rc) return rc;
+    rc = run_bc(c, outb, s);
+    if (rc) return rc;
+    in = outb;
+  }
+  return LES_OK;
+}
+
+int capture_step(les_ctx* c, double* q, double cfl, double dt_fixed) {
+  drop_graph(c);
+  if (!c->cap) HIP_TRY(c, hipStreamCreateWithFlags(&c->cap, hipStreamNonBlocking));
+  HIP_TRY(c, hipStreamBeginCapture(c->cap, hipStreamCaptureModeThreadLocal));
+  int rc = enqueue_step(c, q, cfl, dt_fixed, c->cap);
+  hipGraph_t g = nullptr;
+  hipError_t e = hipStreamEndCapture(c->cap, &g);
+  if (rc) {
+    if (g) (void)hipGraphDestroy(g);
+    return rc;
+  }
+  if (e != hipSuccess) {
+    if (g) (void)hipGraphDestroy(g);
+    c->err = std::string("step capture: ") + hipGetErrorString(e);
+    return LES_EHIP;
+  }
+  e = hipGraphInstantiate(&c->exec, g, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(g);
+  if (e != hipSuccess) {
+    c->exec = nullptr;
+    c->err = std::string("step graph instantiate: ") + hipGetErrorString(e);
+    return LES_EHIP;
+  }
+  c->graph_q = q;
+  c->graph_cfl = cfl;
+  c->graph_dt = dt_fixed;
+  c->graph_tile = c->tile;
+  c->graph_kmin = c->kmin;
+  return LES_OK;
 }
 
 }  // namespace
@@ -683,18 +739,21 @@ int les_step(les_ctx* c, double* q, int nsteps, double cfl, double dt_fixed, dou
   if (mlp_missing(c)) return LES_ESTATE;
   hipStream_t s = (hipStream_t)stream;
   const Dims& D = c->dims;
+  if (!(cfl > 0.0)) cfl = 0.0;
   hipLaunchKernelGGL(k_set_int, dim3(1), dim3(1), 0, s, c->d_flag, 0);
-  for (int n = 0; n < nsteps; ++n) {
+  if (c->use_graph && !c->prof && nsteps > 0) {
+    if (!c->exec || c->graph_q != q || c->graph_cfl != cfl ||
+        (cfl == 0.0 && c->graph_dt != dt_fixed) || c->graph_tile != c->tile ||
+        c->graph_kmin != c->kmin) {
+      int rc = capture_step(c, q, cfl, dt_fixed);
+      if (rc) return rc;
+    }
+    for (int n = 0; n < nsteps; ++n) HIP_TRY(c, hipGraphLaunch(c->exec, s));
+  } else {
     // With cfl > 0 the time step is reduced inside the first stage's node kernel.
-    if (!(cfl > 0.0)) hipLaunchKernelGGL(k_set_scalar, dim3(1), dim3(1), 0, s, c->d_dt, dt_fixed);
-    const double* in = q;
-    for (int l = 0; l < 5; ++l) {
-      double* outb = (l == 4) ? q : ((l % 2 == 0) ? c->qa : c->qb);
-      int rc = run_stage(c, in, 1, outb, q, kAlpha[l], s, (l == 0 && cfl > 0.0) ? cfl : 0.0);
+    for (int n = 0; n < nsteps; ++n) {
+      int rc = enqueue_step(c, q, cfl, dt_fixed, s);
       if (rc) return rc;
-      rc = run_bc(c, outb, s);
-      if (rc) return rc;
-      in = outb;
     }
   }
   hipLaunchKernelGGL(k_check, node_grid(D), dim3(64, 4), 0, s, D, c->phys, q, c->d_flag);
@@ -809,6 +868,13 @@ int les_set_tuning(les_ctx* c, int tile, int kmin) {
   return LES_OK;
 }
 
+int les_set_graph(les_ctx* c, int enable) {
+  if (!c) return LES_EINVAL;
+  c->use_graph = enable != 0;
+  if (!c->use_graph) drop_graph(c);
+  return LES_OK;
+}
+
 int les_tuning_count(void) { return kNumTiles; }
 
 const char* les_tuning_name(int tile) {
@@ -850,6 +916,7 @@ int les_mlp_set_network(les_ctx* c, const float* theta, const les_mlp_norm* norm
   HIP_TRY(c, hipMemcpy(c->mlp_theta, theta, kMlpP * sizeof(float), hipMemcpyDeviceToDevice));
   c->mlp_norm = *norm;
   c->mlp_ready = true;
+  drop_graph(c);  // a captured step holds the normalisation in its kernel arguments
   return LES_OK;
 }
 

@@ -87,6 +87,7 @@ def load():
         lib.les_updated_nodes.argtypes = [vp]
         lib.les_updated_nodes.restype = ctypes.c_longlong
         lib.les_set_tuning.argtypes = [vp, ctypes.c_int, ctypes.c_int]
+        lib.les_set_graph.argtypes = [vp, ctypes.c_int]
         lib.les_tuning_count.argtypes = []
         lib.les_tuning_name.argtypes = [ctypes.c_int]
         lib.les_tuning_name.restype = ctypes.c_char_p
@@ -303,6 +304,9 @@ class Context:
 
     def set_tuning(self, tile, kmin=8):
         self._check(self.lib.les_set_tuning(self.handle, int(tile), int(kmin)), "les_set_tuning")
+
+    def set_graph(self, enable):
+        self._check(self.lib.les_set_graph(self.handle, int(bool(enable))), "les_set_graph")
 
     def tuning_names(self):
         return [self.lib.les_tuning_name(t).decode() for t in range(self.lib.les_tuning_count())]
