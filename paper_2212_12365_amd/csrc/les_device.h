@@ -66,7 +66,7 @@ __device__ __forceinline__ Prim prim_from_q(double r, double mu_, double mv, dou
   s.u = mu_ * ir;
   s.v = mv * ir;
   s.w = mw * ir;
-  s.p = P.gm1 * (e - 0.5 * r * (s.u * s.u + s.v * s.v + s.w * s.w));
+  s.p = P.gm1 * fmadd(-0.5 * r, fmadd(s.w, s.w, fmadd(s.v, s.v, s.u * s.u)), e);
   s.T = P.gamma * s.p * ir;
   return s;
 }
@@ -134,36 +134,37 @@ __device__ __forceinline__ void inviscid_flux(double sx, double sy, double sz, c
   F[4] = (q[4] + s.p) * un;
 }
 
-// Turkel-Vatsa dissipation on a face: D = Lf (eps2 dW - eps4 d3W), with
-// eps2 = k2 max(nuA, nuB), eps4 = max(0, k4 - eps2) (paper, Spatial Discretization).
+// Turkel-Vatsa coefficients of a face (paper, Spatial Discretization): eps2 = k2 max(nuA, nuB)
+// and eps4 = max(0, k4 - eps2); the face's dissipation is Lf (eps2 dW - eps4 d3W).
 template <typename R, typename PP>
-__device__ __forceinline__ void dissipation(R lf, R nuA, R nuB, const R* dW, const R* d3W,
-                                            const PP& P, R* D) {
-  R eps2 = (R)P.k2 * (nuA > nuB ? nuA : nuB);
-  R eps4 = (R)P.k4 - eps2;
-  eps4 = eps4 > (R)0 ? eps4 : (R)0;
-#pragma unroll
-  for (int c = 0; c < 5; ++c) D[c] = lf * fmadd(eps2, dW[c], -(eps4 * d3W[c]));
+__device__ __forceinline__ void dissipation_coefficients(R nuA, R nuB, const PP& P, R* eps2,
+                                                         R* eps4) {
+  *eps2 = (R)P.k2 * (nuA > nuB ? nuA : nuB);
+  const R e4 = (R)P.k4 - *eps2;
+  *eps4 = e4 > (R)0 ? e4 : (R)0;
 }
 
 // Viscous + SGS face flux (paper, Transformation of Coordinates: viscous flux vectors;
-// Subgrid Scale Modeling). Inputs are face values: Sf[9] face-averaged metrics, jinvf the
-// face-averaged J^-1, grad_xi[v][e] the derivative of variable v in {u,v,w,T} along
-// direction e, muf and mutf face-averaged molecular and eddy viscosities, ub the face
-// velocity. d is the face direction. Output F[1..4] (the mass component is zero).
+// Subgrid Scale Modeling). The face metrics, J^-1, molecular and eddy viscosities are the
+// averages of the two nodes' values; they are passed as sums (Ss[9] the metrics, js the J^-1,
+// mus and muts the viscosities), and the halves are folded in exactly: J_f S_f = Ss / js in
+// the gradient, and F_v = (S_f)_d . tau = (Ss)_d . (tau / 2), so the viscosities enter halved
+// once more. grad_xi[v][e] is the derivative of variable v in {u,v,w,T} along direction e, ub
+// the face velocity, d the face direction. Output F[1..4] (the mass component is zero).
 template <typename R, typename PP>
-__device__ __forceinline__ void viscous_flux(const R* Sf, R jinvf, const R gxi[4][3], R muf,
-                                             R mutf, const R* ub, int d, const PP& P, R* F) {
-  R Jf = (R)1 / jinvf;
+__device__ __forceinline__ void viscous_flux(const R* Ss, R js, const R gxi[4][3], R mus,
+                                             R muts, const R* ub, int d, const PP& P, R* F) {
+  const R Jf = (R)1 / js;
   R g[4][3];  // d(var)/dx_n
 #pragma unroll
   for (int v = 0; v < 4; ++v)
 #pragma unroll
     for (int n = 0; n < 3; ++n)
-      g[v][n] = Jf * fmadd(Sf[6 + n], gxi[v][2], fmadd(Sf[3 + n], gxi[v][1], Sf[n] * gxi[v][0]));
-  const R mi = muf * (R)P.inv_re;
-  R visc = mi + mutf;
-  R kappa = fmadd(mi, (R)P.inv_pr, mutf * (R)P.inv_prs) * (R)P.inv_gm1;
+      g[v][n] = Jf * fmadd(Ss[6 + n], gxi[v][2], fmadd(Ss[3 + n], gxi[v][1], Ss[n] * gxi[v][0]));
+  const R mi = mus * (R)P.inv_re;
+  // Half the face values: visc = (mu/Re + mu_t)/2, kappa = [mu/(Re Pr) + mu_t/Pr_t]/(gamma-1)/2.
+  R visc = (R)0.25 * (mi + muts);
+  R kappa = (R)0.25 * fmadd(mi, (R)P.inv_pr, muts * (R)P.inv_prs) * (R)P.inv_gm1;
   R div = g[0][0] + g[1][1] + g[2][2];
   const R c23 = -((R)2 / (R)3);
   R t00 = visc * fmadd(c23, div, (R)2 * g[0][0]);
@@ -175,7 +176,7 @@ __device__ __forceinline__ void viscous_flux(const R* Sf, R jinvf, const R gxi[4
   R bx = fmadd(kappa, g[3][0], fmadd(t02, ub[2], fmadd(t01, ub[1], t00 * ub[0])));
   R by = fmadd(kappa, g[3][1], fmadd(t12, ub[2], fmadd(t11, ub[1], t01 * ub[0])));
   R bz = fmadd(kappa, g[3][2], fmadd(t22, ub[2], fmadd(t12, ub[1], t02 * ub[0])));
-  const R* sd = Sf + 3 * d;
+  const R* sd = Ss + 3 * d;
   F[1] = fmadd(sd[2], t02, fmadd(sd[1], t01, sd[0] * t00));
   F[2] = fmadd(sd[2], t12, fmadd(sd[1], t11, sd[0] * t01));
   F[3] = fmadd(sd[2], t22, fmadd(sd[1], t12, sd[0] * t02));

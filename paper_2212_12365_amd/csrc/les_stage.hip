@@ -486,25 +486,30 @@ template <int d, typename R, typename NA, typename NB>
 __device__ __forceinline__ void face_eval(const NA& a, const NB& b, const R* Wm, const R* Wp,
                                           int m, int n, bool per, const PhysT<R>& Ph, R* H) {
   {  // central inviscid part
-    const R una = a.S(3 * d) * a.f(0) + a.S(3 * d + 1) * a.f(1) + a.S(3 * d + 2) * a.f(2);
-    const R unb = b.S(3 * d) * b.f(0) + b.S(3 * d + 1) * b.f(1) + b.S(3 * d + 2) * b.f(2);
+    const R una = fmadd(a.S(3 * d + 2), a.f(2), fmadd(a.S(3 * d + 1), a.f(1), a.S(3 * d) * a.f(0)));
+    const R unb = fmadd(b.S(3 * d + 2), b.f(2), fmadd(b.S(3 * d + 1), b.f(1), b.S(3 * d) * b.f(0)));
+    // Each node's flux is rounded on its own, identically in the node's two faces along d,
+    // so that it cancels exactly from the node's flux difference.
     const R pa = a.p(), pb = b.p();
     H[0] = (R)0.5 * (a.W(0) * una + b.W(0) * unb);
 #pragma unroll
     for (int c = 1; c < 4; ++c)
-      H[c] = (R)0.5 * ((a.W(c) * una + pa * a.S(3 * d + c - 1)) +
-                       (b.W(c) * unb + pb * b.S(3 * d + c - 1)));
+      H[c] = (R)0.5 * (fmadd(a.W(c), una, pa * a.S(3 * d + c - 1)) +
+                       fmadd(b.W(c), unb, pb * b.S(3 * d + c - 1)));
     H[4] = (R)0.5 * (a.W(4) * una + b.W(4) * unb);
     if constexpr (sizeof(R) == sizeof(float)) {  // the W_ref part of W U
       const R us = (R)0.5 * (una + unb);
 #pragma unroll
-      for (int c = 0; c < 5; ++c) H[c] = H[c] + Ph.wref[c] * us;
+      for (int c = 0; c < 5; ++c) H[c] = fmadd(Ph.wref[c], us, H[c]);
     }
   }
-  {  // artificial dissipation
+  {  // artificial dissipation: H -= Lam_f (eps2 dW - eps4 d3W)
     R dW[5], d3W[5];
 #pragma unroll
     for (int c = 0; c < 5; ++c) dW[c] = b.W(c) - a.W(c);
+    // The third difference is summed left to right with rounded products: it is a small
+    // difference of O(1) values on smooth fields, and this order is the one whose rounding
+    // the residual's cancelling components are held to.
     if (per || (m > 0 && m < n - 2)) {
 #pragma unroll
       for (int c = 0; c < 5; ++c) d3W[c] = Wp[c] - (R)3 * b.W(c) + (R)3 * a.W(c) - Wm[c];
@@ -515,16 +520,17 @@ __device__ __forceinline__ void face_eval(const NA& a, const NB& b, const R* Wm,
 #pragma unroll
       for (int c = 0; c < 5; ++c) d3W[c] = (R)-3 * dW[c] + (a.W(c) - Wm[c]);
     }
-    R Dd[5];
-    dissipation<R>((R)0.5 * (a.lb() + b.lb()), a.nu(), b.nu(), dW, d3W, Ph, Dd);
+    const R lf = (R)0.5 * (a.lb() + b.lb());
+    R eps2, eps4;
+    dissipation_coefficients<R>(a.nu(), b.nu(), Ph, &eps2, &eps4);
 #pragma unroll
-    for (int c = 0; c < 5; ++c) H[c] = H[c] - Dd[c];
+    for (int c = 0; c < 5; ++c) H[c] = fmadd(-lf, fmadd(eps2, dW[c], -(eps4 * d3W[c])), H[c]);
   }
-  {  // viscous and subgrid part
-    R Sf[9];
+  {  // viscous and subgrid part (face averages passed as sums of the two nodes' values)
+    R Ss[9];
 #pragma unroll
-    for (int c = 0; c < 9; ++c) Sf[c] = (R)0.5 * (a.S(c) + b.S(c));
-    const R jf = (R)0.5 * (a.jinv() + b.jinv());
+    for (int c = 0; c < 9; ++c) Ss[c] = a.S(c) + b.S(c);
+    const R js = a.jinv() + b.jinv();
     constexpr int e1 = d == 0 ? 1 : 0, e2 = d == 2 ? 1 : 2;
     R gxi[4][3];
 #pragma unroll
@@ -533,12 +539,12 @@ __device__ __forceinline__ void face_eval(const NA& a, const NB& b, const R* Wm,
       gxi[v][e1] = (R)0.5 * (a.dt(0, v) + b.dt(0, v));
       gxi[v][e2] = (R)0.5 * (a.dt(1, v) + b.dt(1, v));
     }
-    const R muf = (R)0.5 * (a.mu() + b.mu());
-    const R mutf = (R)0.5 * (a.mut() + b.mut());
+    const R mus = a.mu() + b.mu();
+    const R muts = a.mut() + b.mut();
     const R ub[3] = {(R)0.5 * (a.f(0) + b.f(0)), (R)0.5 * (a.f(1) + b.f(1)),
                      (R)0.5 * (a.f(2) + b.f(2))};
     R Fv[5];
-    viscous_flux<R>(Sf, jf, gxi, muf, mutf, ub, d, Ph, Fv);
+    viscous_flux<R>(Ss, js, gxi, mus, muts, ub, d, Ph, Fv);
 #pragma unroll
     for (int c = 1; c < 5; ++c) H[c] = H[c] - Fv[c];
     H[0] = H[0] - (R)0;
