@@ -325,6 +325,51 @@ void les_batch_destroy(les_batch* b);
 const char* les_batch_last_error(const les_batch* b);
 const char* les_last_error(const les_ctx* ctx);
 
+/* ---------------------------------------------------------------------------------------
+ * Far-field noise by the Ffowcs Williams-Hawkings analogy (the paper's Introduction and
+ * Concluding Remarks name it as the route from the jet LES to far-field acoustics; it states
+ * no formulation). Formulation 1A of Farassat for a stationary permeable control surface in a
+ * medium at rest, viscous stresses left out of the loading: with Q_n = rho u.n and
+ * L_i = (p - p0) n_i + rho u_i (u.n) at a surface node y of unit outward normal n and area dS,
+ *   4 pi p'(x, t) = sum_nodes dS [ dQ_n/dtau / r + dL_r/dtau / (c0 r) + L_r / r^2 ]
+ * evaluated at the retarded time tau = t - r/c0, r = |x - y|, L_r = L . (x - y)/r. Time
+ * derivatives are central differences of the samples (second-order one-sided at the first and
+ * last), values at tau linear interpolations between the two samples around it.
+ * ------------------------------------------------------------------------------------- */
+typedef struct les_fwh les_fwh;
+
+/* Control surface on a jet context: the lateral cylinder j = js over i1 <= i <= i2 (every k),
+ * plus the end caps i = i1 (caps bit 0) and i = i2 (caps bit 1) over 0 <= j <= js. Node areas
+ * and normals come from the metric vectors (S_eta on the cylinder, -S_xi and +S_xi on the
+ * caps), with half weights on the edges of each patch. xyz: HOST [3][N] coordinates (those
+ * given to les_init_grid). capacity >= 3: samples the history holds (5 doubles per node and
+ * sample, plus 7 for the sources). dtau > 0: the sampling interval, which the caller keeps
+ * uniform (for instance a sample every m steps of fixed dt). Allocates; synchronous.
+ * LES_EINVAL for a periodic box or indices outside the grid. */
+int les_fwh_create(les_ctx* ctx, const double* xyz, int i1, int i2, int js, int caps,
+                   int capacity, double dtau, les_fwh** out);
+/* Number of surface nodes, and of samples taken. */
+int les_fwh_nodes(const les_fwh* f);
+int les_fwh_samples(const les_fwh* f);
+/* Surface geometry: geo DEVICE [7][ns] = positions (3), unit normals (3), areas. */
+int les_fwh_geometry(les_fwh* f, double* geo, void* stream);
+/* Appends one sample of q (DEVICE [5][N]): rho, u, v, w, p of every surface node.
+ * LES_ESTATE when the history is full. */
+int les_fwh_sample(les_fwh* f, const double* q, void* stream);
+/* Forgets the samples. */
+int les_fwh_reset(les_fwh* f);
+/* Acoustic pressure at no observers (HOST [no][3]) and nt times (HOST [nt]): p_out DEVICE
+ * [no][nt]; scale_out DEVICE [no][nt] or NULL receives the sum of the absolute values of the
+ * terms; skipped HOST or NULL the number of (observer, time, node) triples whose retarded
+ * time fell outside [tau0, tau0 + (samples - 1) dtau] and were left out. Sample m is taken
+ * to be at tau0 + m dtau. Needs 3 samples or more (LES_ESTATE). Synchronises the stream;
+ * may allocate a small observer buffer. */
+int les_fwh_pressure(les_fwh* f, const double* observers, int no, const double* times, int nt,
+                     double c0, double p0, double tau0, double* p_out, double* scale_out,
+                     long long* skipped, void* stream);
+void les_fwh_destroy(les_fwh* f);
+const char* les_fwh_last_error(const les_fwh* f);
+
 #ifdef __cplusplus
 }
 #endif

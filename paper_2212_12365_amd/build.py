@@ -11,7 +11,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "liblesmi.so")
-SOURCES = ["lesmi.hip", "les_stage.hip", "les_batch.hip", "les_mlp.hip"]
+SOURCES = ["lesmi.hip", "les_stage.hip", "les_batch.hip", "les_mlp.hip", "les_fwh.hip"]
 HEADERS = ["les_device.h", "les_common.h", "les_stage.h", "les_bcdt.h", "les_mlp.h"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

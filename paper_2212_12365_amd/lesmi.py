@@ -106,6 +106,20 @@ def load():
         lib.les_batch_destroy.restype = None
         lib.les_batch_last_error.argtypes = [vp]
         lib.les_batch_last_error.restype = ctypes.c_char_p
+        lib.les_fwh_create.argtypes = [vp, dp, ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                                       ctypes.c_int, ctypes.c_int, ctypes.c_double,
+                                       ctypes.POINTER(vp)]
+        lib.les_fwh_nodes.argtypes = [vp]
+        lib.les_fwh_samples.argtypes = [vp]
+        lib.les_fwh_geometry.argtypes = [vp, vp, vp]
+        lib.les_fwh_sample.argtypes = [vp, vp, vp]
+        lib.les_fwh_reset.argtypes = [vp]
+        lib.les_fwh_pressure.argtypes = [vp, dp, ctypes.c_int, dp, ctypes.c_int, ctypes.c_double,
+                                         ctypes.c_double, ctypes.c_double, vp, vp,
+                                         ctypes.POINTER(ctypes.c_longlong), vp]
+        lib.les_fwh_destroy.argtypes = [vp]
+        lib.les_fwh_last_error.argtypes = [vp]
+        lib.les_fwh_last_error.restype = ctypes.c_char_p
         fp = ctypes.c_void_p
         np_ = ctypes.POINTER(les_mlp_norm)
         lib.les_mlp_set_network.argtypes = [vp, fp, np_]
@@ -537,3 +551,69 @@ def filter_target(fine, coarse, q_fine, smin, stream=None):
     if rc != LES_OK:
         raise LesError(rc, "les_filter_target", load().les_last_error(coarse.handle).decode())
     return out
+
+
+class FWH:
+    """Ffowcs Williams-Hawkings control surface of a jet context (les_fwh_create ..
+    les_fwh_destroy)."""
+
+    def __init__(self, ctx, xyz, i1, i2, js, caps=3, capacity=256, dtau=1.0):
+        self.lib = load()
+        self.ctx = ctx
+        xyz = np.ascontiguousarray(xyz, dtype=np.float64)
+        h = ctypes.c_void_p()
+        rc = self.lib.les_fwh_create(ctx.handle,
+                                     xyz.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                     int(i1), int(i2), int(js), int(caps), int(capacity),
+                                     float(dtau), ctypes.byref(h))
+        self.handle = h
+        if rc != LES_OK:
+            msg = self.lib.les_fwh_last_error(h).decode() if h.value else ""
+            if h.value:
+                self.lib.les_fwh_destroy(h)
+            raise LesError(rc, "les_fwh_create", msg)
+        self.ns = self.lib.les_fwh_nodes(h)
+
+    def _check(self, rc, what):
+        if rc != LES_OK:
+            raise LesError(rc, what, self.lib.les_fwh_last_error(self.handle).decode())
+
+    def geometry(self, stream=None):
+        """[7][ns] float64 GPU tensor: positions (3), unit normals (3), areas."""
+        import torch
+        g = torch.empty((7, self.ns), dtype=torch.float64, device="cuda")
+        self._check(self.lib.les_fwh_geometry(self.handle, _dev(g, 7 * self.ns, "geo"),
+                                              _stream(stream)), "les_fwh_geometry")
+        return g
+
+    def sample(self, q, stream=None):
+        self._check(self.lib.les_fwh_sample(self.handle, _dev(q, 5 * self.ctx.n, "q"),
+                                            _stream(stream)), "les_fwh_sample")
+
+    def samples(self):
+        return self.lib.les_fwh_samples(self.handle)
+
+    def reset(self):
+        self._check(self.lib.les_fwh_reset(self.handle), "les_fwh_reset")
+
+    def pressure(self, observers, times, c0, p0, tau0=0.0, stream=None):
+        """(p' [no][nt], scale [no][nt]) float64 GPU tensors and the skipped count."""
+        import torch
+        obs = np.ascontiguousarray(observers, dtype=np.float64).reshape(-1, 3)
+        tt = np.ascontiguousarray(times, dtype=np.float64).reshape(-1)
+        no, nt = obs.shape[0], tt.size
+        p = torch.empty((no, nt), dtype=torch.float64, device="cuda")
+        sc = torch.empty_like(p)
+        sk = ctypes.c_longlong(0)
+        dp = ctypes.POINTER(ctypes.c_double)
+        self._check(self.lib.les_fwh_pressure(self.handle, obs.ctypes.data_as(dp), no,
+                                              tt.ctypes.data_as(dp), nt, float(c0), float(p0),
+                                              float(tau0), _dev(p, no * nt, "p"),
+                                              _dev(sc, no * nt, "scale"), ctypes.byref(sk),
+                                              _stream(stream)), "les_fwh_pressure")
+        return p, sc, sk.value
+
+    def close(self):
+        if self.handle and self.handle.value:
+            self.lib.les_fwh_destroy(self.handle)
+            self.handle = ctypes.c_void_p()

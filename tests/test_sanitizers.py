@@ -42,7 +42,7 @@ def test_oracle_runs_clean_under_asan_and_ubsan(tmp_path):
 HIPCC = "/opt/rocm/bin/hipcc"
 CLANG = "/opt/rocm/llvm/bin/clang"
 CSRC = os.path.join(ROOT, "paper_2212_12365_amd", "csrc")
-SOURCES = ["lesmi.hip", "les_stage.hip", "les_batch.hip", "les_mlp.hip"]
+SOURCES = ["lesmi.hip", "les_stage.hip", "les_batch.hip", "les_mlp.hip", "les_fwh.hip"]
 
 
 @pytest.mark.skipif(not (os.path.exists(HIPCC) and os.path.exists(CLANG)),
