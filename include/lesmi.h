@@ -131,6 +131,26 @@ int les_residual(les_ctx* ctx, const double* q, double* rhs, void* stream);
 int les_step(les_ctx* ctx, double* q, int nsteps, double cfl, double dt_fixed,
              double* dt_last, void* stream);
 
+/* Dual time stepping (the paper's Concluding Remarks ask for a dual-time procedure to lift its
+ * explicit time step; the low-Mach preconditioning of the pseudo-time term is not part of
+ * this one). Advances q (DEVICE [5][N], in place) by nsteps physical steps of size dt of the
+ * backward-difference discretisation (a0 Q^{n+1} + a1 Q^n + a2 Q^{n-1})/dt + J RHS(Q^{n+1}) = 0,
+ * (a0, a1, a2) = (3/2, -2, 1/2), or (1, -1, 0) (backward Euler) for a first step without
+ * history. Each step takes `subiters` pseudo-time iterations of the five-stage scheme
+ * (alpha = 1/4, 1/6, 3/8, 1/2, 1) with the local pseudo-time step
+ * dtau_i = cfl_tau J^-1 / sum_d (|S_d.u| + a|S_d|) of the iteration's starting state, the
+ * physical-time term point-implicit:
+ *   Q^(l) = [Q^(0) - alpha_l dtau (J RHS(Q^(l-1)) + (a1 Q^n + a2 Q^{n-1})/dt)]
+ *           / (1 + alpha_l dtau a0 / dt),
+ * and the boundary conditions after every stage. q_prev (DEVICE [5][N], may be NULL) holds
+ * Q^{n-1} on entry (NULL: the first step is backward Euler) and receives Q^n of the last step
+ * on return, so that calls chain. res_out (HOST [nsteps * subiters], may be NULL) receives
+ * the r.m.s. over updated nodes of the unsteady mass residual at the start of every
+ * iteration. The first call allocates four state-sized buffers; synchronises once, at the
+ * end. Errors as les_step. */
+int les_dual_step(les_ctx* ctx, double* q, double* q_prev, int nsteps, double dt,
+                  int subiters, double cfl_tau, double* res_out, void* stream);
+
 /* Smagorinsky eddy viscosity mu_sgs = rho (C_s Delta)^2 (2 S_ij S_ij)^(1/2) at every node
  * (paper, Subgrid Scale Viscosity), Delta = (J^-1)^(1/3), 0 where J^-1 <= 0. q DEVICE
  * [5][N], mu_t DEVICE [N], in units of rho_ref a_ref L_ref. */

@@ -96,6 +96,16 @@ struct les_ctx {
   std::vector<hipEvent_t> ev;
   size_t nrec = 0;
 
+  // Dual time stepping: Q^n and Q^(n-1) [5][N], the residual of a stage [5][N], the local
+  // pseudo-time steps [N] (allocated by the first les_dual_step), and the device record of
+  // the unsteady residual norms.
+  double* dual_qn = nullptr;
+  double* dual_qm = nullptr;
+  double* dual_rhs = nullptr;
+  double* dual_dtau = nullptr;
+  double* dual_res = nullptr;
+  int dual_res_cap = 0;
+
   // One Runge-Kutta step captured in a HIP graph (on the context's own non-blocking stream)
   // and replayed on the caller's stream; recaptured when the state pointer, the time-step
   // mode or value, the launch tuning or the network normalisation changes.

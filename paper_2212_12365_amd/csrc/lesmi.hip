@@ -344,6 +344,96 @@ __global__ void k_rhs_norm_final(const double* __restrict__ part, int nparts, do
 }
 
 // ---------------------------------------------------------------------------------------
+// Dual time stepping (the paper's Concluding Remarks ask for it): physical time by the
+// backward difference (a0 Q^{n+1} + a1 Q^n + a2 Q^{n-1})/dt + J RHS = 0, solved by pseudo-time
+// iterations of the five-stage scheme with local pseudo-time steps and the physical-time term
+// point-implicit in each stage.
+// ---------------------------------------------------------------------------------------
+
+// Local pseudo-time step cfl_tau J^-1 / sum_d (|S_d . u| + a |S_d|) at updated nodes, 0
+// elsewhere, from the state q.
+__global__ void k_local_dtau(Dims D, Phys P, const double* __restrict__ q,
+                             const double* __restrict__ S, const double* __restrict__ jinv,
+                             double cfl_tau, double* __restrict__ dtau) {
+  const long long o = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (o >= D.N) return;
+  const long long N = D.N;
+  const int i = (int)(o % D.n[0]), j = (int)((o / D.n[0]) % D.n[1]),
+            k = (int)(o / ((long long)D.n[0] * D.n[1]));
+  if (!is_updated(D, i, j, k)) {
+    dtau[o] = 0.0;
+    return;
+  }
+  const Prim s = prim_from_q(q[o], q[N + o], q[2 * N + o], q[3 * N + o], q[4 * N + o], P);
+  const double a = sqrt(s.T);
+  double lam = 0.0;
+  for (int d = 0; d < 3; ++d)
+    lam += spectral(S[(3 * d) * N + o], S[(3 * d + 1) * N + o], S[(3 * d + 2) * N + o], s.u, s.v,
+                    s.w, a);
+  dtau[o] = cfl_tau * jinv[o] / lam;
+}
+
+struct DualArgs {
+  Dims D;
+  const double* q0;    // state at the start of the pseudo-time iteration
+  const double* rhs;   // residual of the stage input
+  const double* qn;    // Q^n
+  const double* qm;    // Q^(n-1) (unused when a2 = 0)
+  const double* dtau;  // local pseudo-time steps
+  const double* jac;   // J at updated nodes
+  double alpha, a0, a1, a2, dt;
+  double* out;         // stage output (updated nodes only)
+  double* part;        // per-block sums of the squared unsteady mass residual, or null
+  long long chunk;     // nodes per block
+};
+
+// Q^(l) = [Q^(0) - alpha dtau (J RHS + (a1 Q^n + a2 Q^{n-1})/dt)] / (1 + alpha dtau a0/dt) at
+// the updated nodes of the block's node range; with part, also the block's sum of squares of
+// the unsteady mass residual (a0 Q^(0) + a1 Q^n + a2 Q^{n-1})/dt + J RHS (first stage).
+__global__ void __launch_bounds__(256) k_dual_update(DualArgs A) {
+  __shared__ double red[256];
+  const Dims& D = A.D;
+  const long long N = D.N;
+  const long long lo = (long long)blockIdx.x * A.chunk;
+  const long long hi = lo + A.chunk < N ? lo + A.chunk : N;
+  double s2 = 0.0;
+  for (long long o = lo + threadIdx.x; o < hi; o += blockDim.x) {
+    const int i = (int)(o % D.n[0]), j = (int)((o / D.n[0]) % D.n[1]),
+              k = (int)(o / ((long long)D.n[0] * D.n[1]));
+    if (!is_updated(D, i, j, k)) continue;
+    const double J = A.jac[o], dtau = A.dtau[o];
+    const double den = 1.0 + A.alpha * dtau * A.a0 / A.dt;
+    for (int c = 0; c < 5; ++c) {
+      const long long e = c * N + o;
+      const double jr = J * A.rhs[e];
+      const double hist = A.a2 != 0.0 ? A.a1 * A.qn[e] + A.a2 * A.qm[e] : A.a1 * A.qn[e];
+      if (c == 0 && A.part) {
+        const double r = (A.a0 * A.q0[e] + hist) / A.dt + jr;
+        s2 += r * r;
+      }
+      A.out[e] = (A.q0[e] - A.alpha * dtau * (jr + hist / A.dt)) / den;
+    }
+  }
+  if (!A.part) return;
+  red[threadIdx.x] = s2;
+  __syncthreads();
+  for (int h = 128; h > 0; h >>= 1) {
+    if ((int)threadIdx.x < h) red[threadIdx.x] += red[threadIdx.x + h];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) A.part[blockIdx.x] = red[0];
+}
+
+// out[0] = sqrt(sum of the block sums, in block order / nupd).
+__global__ void k_dual_res_final(const double* __restrict__ part, int nparts, double nupd,
+                                 double* __restrict__ out) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  double s = 0.0;
+  for (int b = 0; b < nparts; ++b) s += part[b];
+  out[0] = sqrt(s / nupd);
+}
+
+// ---------------------------------------------------------------------------------------
 // Host side.
 // ---------------------------------------------------------------------------------------
 int fail(les_ctx* c, int code, const char* msg) {
@@ -446,7 +536,8 @@ void free_ctx(les_ctx* c) {
   void* ptrs[] = {c->S, c->jinv, c->jac, c->bc.nff, c->bc.nin, c->bc.nex, c->bc.jetmask,
                   c->bc.axis, c->qa, c->qb, c->rec, c->S32, c->rec32, c->d_dt, c->d_dtpart,
                   c->d_flag, c->d_partial, c->d_diag, c->mlp_theta, c->mlp_feat,
-                  c->mlp_scale, c->mlp_fallback, c->stat_sum, c->stat_sq};
+                  c->mlp_scale, c->mlp_fallback, c->stat_sum, c->stat_sq, c->dual_qn,
+                  c->dual_qm, c->dual_rhs, c->dual_dtau, c->dual_res};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
 }
@@ -765,6 +856,87 @@ int les_step(les_ctx* c, double* q, int nsteps, double cfl, double dt_fixed, dou
   HIP_TRY(c, hipMemcpyAsync(&dt, c->d_dt, sizeof(double), hipMemcpyDeviceToHost, s));
   HIP_TRY(c, hipStreamSynchronize(s));
   if (dt_last) *dt_last = dt;
+  if (flag) return fail(c, LES_ENONFINITE, "non-finite value or non-positive density/pressure");
+  return LES_OK;
+}
+
+int les_dual_step(les_ctx* c, double* q, double* q_prev, int nsteps, double dt, int subiters,
+                  double cfl_tau, double* res_out, void* stream) {
+  if (!c || !q || nsteps < 0 || subiters < 1 || !(dt > 0.0) || !(cfl_tau > 0.0))
+    return fail(c, LES_EINVAL, "bad argument");
+  if (mlp_missing(c)) return LES_ESTATE;
+  hipStream_t s = (hipStream_t)stream;
+  const Dims& D = c->dims;
+  const long long N = D.N;
+  if (!c->dual_qn && (dev_alloc(c, &c->dual_qn, 5 * N) || dev_alloc(c, &c->dual_qm, 5 * N) ||
+                      dev_alloc(c, &c->dual_rhs, 5 * N) || dev_alloc(c, &c->dual_dtau, N)))
+    return LES_ENOMEM;
+  const long long nres = (long long)nsteps * subiters;
+  if (nres > c->dual_res_cap) {
+    if (c->dual_res) (void)hipFree(c->dual_res);
+    c->dual_res = nullptr;
+    c->dual_res_cap = 0;
+    if (dev_alloc(c, &c->dual_res, (size_t)nres)) return LES_ENOMEM;
+    c->dual_res_cap = (int)nres;
+  }
+  const size_t bytes = sizeof(double) * 5 * N;
+  bool have_prev = q_prev != nullptr;
+  if (have_prev) HIP_TRY(c, hipMemcpyAsync(c->dual_qm, q_prev, bytes, hipMemcpyDeviceToDevice, s));
+  long long chunk = (N + kMaxPartials - 1) / kMaxPartials;
+  if (chunk < 1024) chunk = 1024;
+  const int nparts = (int)((N + chunk - 1) / chunk);
+  hipLaunchKernelGGL(k_set_int, dim3(1), dim3(1), 0, s, c->d_flag, 0);
+  for (int n = 0; n < nsteps; ++n) {
+    const double a0 = have_prev ? 1.5 : 1.0, a1 = have_prev ? -2.0 : -1.0,
+                 a2 = have_prev ? 0.5 : 0.0;
+    HIP_TRY(c, hipMemcpyAsync(c->dual_qn, q, bytes, hipMemcpyDeviceToDevice, s));
+    for (int it = 0; it < subiters; ++it) {
+      hipLaunchKernelGGL(k_local_dtau, dim3(grid_for(N)), dim3(kBlock), 0, s, D, c->phys, q, c->S,
+                         c->jinv, cfl_tau, c->dual_dtau);
+      const double* in = q;
+      for (int l = 0; l < 5; ++l) {
+        double* outb = (l == 4) ? q : ((l % 2 == 0) ? c->qa : c->qb);
+        int rc = run_stage(c, in, 0, c->dual_rhs, nullptr, 0.0, s);
+        if (rc) return rc;
+        DualArgs A;
+        A.D = D;
+        A.q0 = q;
+        A.rhs = c->dual_rhs;
+        A.qn = c->dual_qn;
+        A.qm = have_prev ? c->dual_qm : c->dual_qn;
+        A.dtau = c->dual_dtau;
+        A.jac = c->jac;
+        A.alpha = kAlpha[l];
+        A.a0 = a0;
+        A.a1 = a1;
+        A.a2 = a2;
+        A.dt = dt;
+        A.out = outb;
+        A.part = l == 0 ? c->d_partial : nullptr;
+        A.chunk = chunk;
+        hipLaunchKernelGGL(k_dual_update, dim3(nparts), dim3(256), 0, s, A);
+        if (l == 0)
+          hipLaunchKernelGGL(k_dual_res_final, dim3(1), dim3(1), 0, s, c->d_partial, nparts,
+                             (double)c->n_updated, c->dual_res + (size_t)n * subiters + it);
+        rc = run_bc(c, outb, s);
+        if (rc) return rc;
+        in = outb;
+      }
+    }
+    HIP_TRY(c, hipMemcpyAsync(c->dual_qm, c->dual_qn, bytes, hipMemcpyDeviceToDevice, s));
+    have_prev = true;
+  }
+  if (q_prev && nsteps > 0)
+    HIP_TRY(c, hipMemcpyAsync(q_prev, c->dual_qm, bytes, hipMemcpyDeviceToDevice, s));
+  hipLaunchKernelGGL(k_check, node_grid(D), dim3(64, 4), 0, s, D, c->phys, q, c->d_flag);
+  int rc = launch_check(c, "dual time step kernels");
+  if (rc) return rc;
+  int flag = 0;
+  HIP_TRY(c, hipMemcpyAsync(&flag, c->d_flag, sizeof(int), hipMemcpyDeviceToHost, s));
+  if (res_out && nres > 0)
+    HIP_TRY(c, hipMemcpyAsync(res_out, c->dual_res, sizeof(double) * nres,
+                              hipMemcpyDeviceToHost, s));
+  HIP_TRY(c, hipStreamSynchronize(s));
   if (flag) return fail(c, LES_ENONFINITE, "non-finite value or non-positive density/pressure");
   return LES_OK;
 }

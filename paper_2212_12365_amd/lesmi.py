@@ -88,6 +88,8 @@ def load():
         lib.les_updated_nodes.restype = ctypes.c_longlong
         lib.les_set_tuning.argtypes = [vp, ctypes.c_int, ctypes.c_int]
         lib.les_set_graph.argtypes = [vp, ctypes.c_int]
+        lib.les_dual_step.argtypes = [vp, vp, vp, ctypes.c_int, ctypes.c_double, ctypes.c_int,
+                                      ctypes.c_double, dp, vp]
         lib.les_tuning_count.argtypes = []
         lib.les_tuning_name.argtypes = [ctypes.c_int]
         lib.les_tuning_name.restype = ctypes.c_char_p
@@ -249,6 +251,16 @@ class Context:
                                       float(cfl), float(dt_fixed), ctypes.byref(dt),
                                       _stream(stream)), "les_step")
         return dt.value
+
+    def dual_step(self, q, nsteps, dt, subiters, cfl_tau, q_prev=None, stream=None):
+        """les_dual_step; returns the residual history [nsteps][subiters] (numpy)."""
+        res = np.zeros(max(nsteps * subiters, 1))
+        prev = _dev(q_prev, 5 * self.n, "q_prev") if q_prev is not None else None
+        self._check(self.lib.les_dual_step(self.handle, _dev(q, 5 * self.n, "q"), prev,
+                                           int(nsteps), float(dt), int(subiters), float(cfl_tau),
+                                           res.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                           _stream(stream)), "les_dual_step")
+        return res[:nsteps * subiters].reshape(nsteps, subiters)
 
     def sgs_viscosity(self, q, mu_t=None, stream=None):
         import torch
