@@ -306,6 +306,10 @@ def main():
     ap.add_argument("--sweep-grids", default="",
                     help="with --mesh-sweep: grids to time instead of the paper's meshes, "
                          "e.g. 768x384x384,384x192x192")
+    ap.add_argument("--closure-only", action="store_true",
+                    help="only train the closure network briefly (256x128x128 FP64 run filtered "
+                         "onto 128x64x64) and time learned-closure steps of the 384x192x192 "
+                         "mixed jet (for counter runs of the closure kernels), then exit")
     ap.add_argument("--mixed-only", action="store_true",
                     help="only time the mixed-precision form of the jet workload and print its "
                          "figures (for counter runs of its kernels), then exit")
@@ -342,6 +346,29 @@ def main():
         print(json.dumps({"mesh_sweep": rows, "unit": "Mcell-RKstage/s", "steps": args.steps,
                           "warmup": args.warmup, "workload": "synthetic jet, CFL 0.5, Smagorinsky"}),
               flush=True)
+        return
+    if args.closure_only:
+        from paper_2212_12365_amd import closure
+        from paper_2212_12365_amd.lesmi import Context
+        t0 = time.perf_counter()
+        trained = closure.run((256, 128, 128), spinup=100, every=50, count=3, steps=100,
+                              batch=4096, post_steps=0, log=lambda m: None, return_network=True)
+        t_train = time.perf_counter() - t0
+        p3, xyz3, q3 = sy.make_case("jet", (384, 192, 192), seed=0)
+        cm = Context(p3.replace(precision=1, closure=1), xyz3)
+        cm.mlp_set_network(trained["theta"], trained["norm"])
+        g = torch.from_numpy(q3).to("cuda")
+        cm.apply_bc(g)
+        cm.step(g, args.warmup, cfl=0.5)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        cm.step(g, args.steps, cfl=0.5)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        print(json.dumps({"form": "mixed + learned closure", "workload": "jet 384x192x192",
+                          "ms_per_step": round(wall * 1e3 / max(args.steps, 1), 3),
+                          "training_s": round(t_train, 2),
+                          "heldout_gain_vs_cs2": round(trained["gain"], 4)}), flush=True)
         return
     params, xyz, q = sy.make_case("jet", JET_GRID, seed=0)
     if args.mixed_only:
