@@ -117,43 +117,61 @@ def stack(snaps, key):
 
 
 def aposteriori(fine, coarse, xyzc, q_fine, q_start, theta, norm, fine_steps, smin,
-                log=print):
+                checkpoints=1, log=print):
     """A-posteriori comparison: from the filtered state q_start, coarse runs (mixed form)
     with the Smagorinsky closure and with the learned closure advance over the time the fine
     run advances in `fine_steps` steps (coarse dt = 2 x the fine run's dt, fixed), and their
-    velocity fields are compared with the filtered fine solution at that time."""
+    velocity fields are compared with the filtered fine solution at `checkpoints` equally
+    spaced times (the last one at the end). Returns the relative L2 errors of u at each
+    checkpoint, per closure."""
     import torch
     from .lesmi import Context
+    checkpoints = max(1, int(checkpoints))
+    seg = fine_steps // checkpoints
+    seg -= seg % 2
+    if seg < 2:
+        raise ValueError("fine_steps too small for the checkpoints")
     dt_f = fine.step(q_fine, 1, cfl=0.5)
-    fine.step(q_fine, fine_steps - 1, cfl=0.0, dt_fixed=dt_f)
-    ref = lesmi.filter_target(fine, coarse, q_fine, smin)["q"]
+    refs = []
+    for m in range(checkpoints):
+        fine.step(q_fine, seg - 1 if m == 0 else seg, cfl=0.0, dt_fixed=dt_f)
+        ref = lesmi.filter_target(fine, coarse, q_fine, smin)["q"]
+        refs.append(ref[1:4] / ref[0])
+        log(f"a-posteriori: fine reference {m + 1}/{checkpoints}")
     coarse_params = coarse.params
-    u_ref = ref[1:4] / ref[0]
-    out = {"fine_dt": dt_f, "coarse_steps": fine_steps // 2}
+    out = {"fine_dt": dt_f, "coarse_steps": [(m + 1) * (seg // 2) for m in range(checkpoints)]}
+    inner = (slice(None), slice(None), slice(1, -1), slice(1, -1))
     for name, closure_id in (("smagorinsky", 0), ("learned", 1)):
         c = Context(coarse_params.replace(precision=1, closure=closure_id), xyzc)
         if closure_id == 1:
             c.mlp_set_network(theta, norm)
         g = q_start.clone()
         c.apply_bc(g)
-        c.step(g, fine_steps // 2, cfl=0.0, dt_fixed=2.0 * dt_f)
-        u = g[1:4] / g[0]
-        inner = (slice(None), slice(None), slice(1, -1), slice(1, -1))
-        err = torch.linalg.vector_norm((u - u_ref)[inner]) / torch.linalg.vector_norm(u_ref[inner])
-        out[f"u_rel_l2_{name}"] = float(err)
+        errs = []
+        for m in range(checkpoints):
+            c.step(g, seg // 2, cfl=0.0, dt_fixed=2.0 * dt_f)
+            u = g[1:4] / g[0]
+            u_ref = refs[m]
+            err = (torch.linalg.vector_norm((u - u_ref)[inner]) /
+                   torch.linalg.vector_norm(u_ref[inner]))
+            errs.append(float(err))
+        out[f"u_rel_l2_{name}"] = errs
         if closure_id == 1:
             out["fallback_evaluations"] = c.mlp_fallback_count()
         c.close()
-        log(f"a-posteriori {name}: u rel-L2 vs filtered fine {float(err):.4e}")
+        log(f"a-posteriori {name}: u rel-L2 vs filtered fine at coarse steps "
+            f"{out['coarse_steps']}: " + ", ".join(f"{e:.4e}" for e in errs))
     return out
 
 
 def run(fine_shape=(768, 384, 384), spinup=1200, every=200, count=3, steps=600, batch=8192,
-        lr=2e-3, seed=0, smin=1.0, post_steps=400, log=print, return_network=False):
+        lr=2e-3, seed=0, smin=1.0, post_steps=1000, checkpoints=5, log=print,
+        return_network=False):
     """End-to-end training of the closure on the jet: an FP64 run on the fine grid (seeded
     jet field), `count` snapshots box-filtered onto the grid of half the nodes per direction,
     training on all but the last snapshot and evaluation on the last; then, if post_steps > 0,
-    the a-posteriori comparison over post_steps fine steps. Returns a dict (with the trained
+    the a-posteriori comparison over post_steps fine steps at `checkpoints` equally spaced
+    times. Returns a dict (with the trained
     network under "theta" and "norm" if return_network)."""
     import time as _time
     import torch
@@ -200,7 +218,7 @@ def run(fine_shape=(768, 384, 384), spinup=1200, every=200, count=3, steps=600, 
                 "losses": losses, "fine_run_s": round(t_run, 1), "train_s": round(t_train, 2)})
     if post_steps > 0:
         res["aposteriori"] = aposteriori(fine, coarse, xyzc, g, test["q"], theta, norm,
-                                         post_steps, smin, log)
+                                         post_steps, smin, checkpoints, log)
     fine.close()
     coarse.close()
     if return_network:
@@ -221,8 +239,10 @@ if __name__ == "__main__":
     ap.add_argument("--count", type=int, default=3)
     ap.add_argument("--steps", type=int, default=600)
     ap.add_argument("--batch", type=int, default=8192)
-    ap.add_argument("--post-steps", type=int, default=400)
+    ap.add_argument("--post-steps", type=int, default=1000)
+    ap.add_argument("--checkpoints", type=int, default=5)
     a = ap.parse_args()
     out = run(tuple(int(x) for x in a.fine.split(",")), a.spinup, a.every, a.count, a.steps,
-              a.batch, post_steps=a.post_steps, log=lambda m: print(m, flush=True))
+              a.batch, post_steps=a.post_steps, checkpoints=a.checkpoints,
+              log=lambda m: print(m, flush=True))
     print(json.dumps(out), flush=True)
