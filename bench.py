@@ -211,8 +211,9 @@ def run_batched(torch, steps, warmup):
 def run_c3(torch, steps, warmup):
     """The 384 x 192 x 192 jet: the mixed form stepped beside the FP64 form from the same
     state (relative errors of rho, u and E after `steps` steps), and the mixed form with the
-    learned closure against the mixed form with Smagorinsky (throughput; the network holds
-    its seeded initial weights, which do not change the work)."""
+    learned closure against the mixed form with Smagorinsky (throughput, with a network
+    trained briefly on a filtered 256 x 128 x 128 run and its training data's input range,
+    so the fallback acts where the flow leaves that range)."""
     import synthetic as sy
     from paper_2212_12365_amd import closure
     from paper_2212_12365_amd.lesmi import Context
@@ -284,6 +285,210 @@ def copy_calibration(gib=1.0, reps=5):
                       "reps": reps}), flush=True)
 
 
+# Algorithmic bytes per node: one running-statistics sample reads q (40 B) and reads and
+# writes the sums and the sums of squares (5 + 5 FP64 each: 160 B).
+STATS_BYTES_PER_NODE = 200
+# A dual-time pseudo-stage: the residual launch reads Q^(l-1) (40 B), the metrics and J^-1
+# (80 B) and writes the residual (40 B); the update reads Q^(0), the residual, Q^n (and
+# Q^(n-1) for the second-order step), the local pseudo-time step and J, and writes Q^(l)
+# (176 B for the backward-Euler first step); once per iteration the local pseudo-time step
+# reads q, the metrics and J^-1 and writes it (128 B).
+DUAL_BYTES_PER_NODE_STAGE = 160 + 176
+DUAL_BYTES_PER_NODE_ITER = 128
+# Far-field noise: floating-point operations of one (observer, time, surface node) term of
+# the surface integral, counting each division and square root as one: the distance and
+# its unit vector (12), the retarded time and the interpolation weight (5), the seven
+# interpolated sources (21), the two projections (10), the three terms and the sums (12).
+FWH_FLOP_PER_TERM = 60
+FP64_VECTOR_PEAK_TFLOPS = 78.6
+
+
+def event_time(torch, fn, reps):
+    """Average GPU time of fn() over reps calls, from HIP events on torch's current stream
+    (the stream the library launches on when no stream is given)."""
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record()
+    for _ in range(reps):
+        fn()
+    e1.record()
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / 1e3 / reps
+
+
+def run_rows(torch, cpu=True):
+    """The rows beyond the explicit step on the 256 x 128 x 128 jet, each timed on the GPU and
+    set against its roofline, with the oracle timed beside it on a bounded sample:
+    * running statistics: one les_stats_accumulate sample (HBM-bound: 200 B per node), and
+      the azimuthal reduction;
+    * far-field noise: les_fwh_pressure on a control surface around the jet (x from 2 to 6,
+      r = 1.5, both caps) with 256 samples of an acoustic monopole field, 64 observers on an
+      arc at 30 jet diameters and 256 observer times (FP64 arithmetic-bound);
+    * dual time: one backward-Euler physical step of four times the explicit CFL-0.5 step,
+      four pseudo-time iterations at cfl_tau 1."""
+    import math
+    import numpy as np
+    import oracle
+    import synthetic as sy
+    from oracle import dualtime, fwh
+    from oracle.stats import RunningStats
+    from paper_2212_12365_amd.lesmi import FWH, Context
+    p, xyz, q = sy.make_case("jet", JET_GRID, seed=0)
+    N = p.ni * p.nj * p.nk
+    ctx = Context(p, xyz)
+    g = torch.from_numpy(q).cuda()
+    ctx.apply_bc(g)
+    upd = ctx.updated_nodes()
+    rows = {}
+
+    # Running statistics.
+    ctx.stats_reset()
+    ctx.stats_accumulate(g)
+    t_acc = event_time(torch, lambda: ctx.stats_accumulate(g), 50)
+    t_az = event_time(torch, lambda: ctx.stats_azimuthal(), 5)
+    gbs = STATS_BYTES_PER_NODE * N / t_acc / 1e9
+    st = {"workload": "jet 256x128x128 FP64 state, one sample per call",
+          "accumulate_us": round(t_acc * 1e6, 2),
+          "value": round(N / t_acc / 1e6, 1), "unit": "Mnode-samples/s",
+          "azimuthal_reduction_us": round(t_az * 1e6, 2),
+          "roofline": {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS,
+                       "unit": "GB/s", "frac": round(gbs / HBM_PEAK_GBS, 4),
+                       "kernel": "k_stats_acc", "bytes_per_node": STATS_BYTES_PER_NODE}}
+    if cpu:
+        ctx_state = g.cpu().numpy()
+        rs = RunningStats(p.shape, p.gamma)
+        t0 = time.perf_counter()
+        for _ in range(3):
+            rs.add(ctx_state)
+        t_o = (time.perf_counter() - t0) / 3
+        st["oracle"] = {"value": round(N / t_o / 1e6, 2), "unit": "Mnode-samples/s",
+                        "kind": "oracle", "cores": 1,
+                        "sample": f"3 samples of the same state (numpy), {t_o:.2f} s each"}
+    rows["f1_statistics"] = st
+
+    # Dual time.
+    g2 = g.clone()
+    dt_expl = ctx.step(g2, 1, cfl=0.5)
+    dt = 4.0 * dt_expl
+    sub = 4
+    g2.copy_(g)
+    ctx.dual_step(g2, 1, dt, 1, 1.0)  # allocates the buffers; warm-up
+    walls = []
+    for _ in range(REPEATS):
+        g2.copy_(g)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        res = ctx.dual_step(g2, 1, dt, sub, 1.0)
+        walls.append(time.perf_counter() - t0)
+    t_d = median(walls)
+    rate = upd * 5 * sub / t_d / 1e6
+    bpn = DUAL_BYTES_PER_NODE_STAGE + DUAL_BYTES_PER_NODE_ITER / 5.0
+    gbs = rate * 1e6 * bpn / 1e9
+    du = {"workload": "jet 256x128x128 FP64, one backward-Euler step of 4x the explicit "
+                      "CFL-0.5 step, 4 pseudo-time iterations at cfl_tau 1",
+          "ms_per_physical_step": round(t_d * 1e3, 3),
+          "value": round(rate, 1), "unit": "Mcell-pseudo-stage/s",
+          "residual_history": [float(x) for x in res[0]],
+          "roofline": {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS,
+                       "unit": "GB/s", "frac": round(gbs / HBM_PEAK_GBS, 4),
+                       "bytes_per_node_stage": bpn}}
+    if cpu:
+        o = oracle.Oracle(p, xyz)
+        qo = o.apply_bc(q)
+        t0 = time.perf_counter()
+        dualtime.dual_step(o, qo, None, 1, dt, 1, 1.0)
+        t_o = time.perf_counter() - t0
+        du["oracle"] = {"value": round(upd * 5 / t_o / 1e6, 2), "unit": "Mcell-pseudo-stage/s",
+                        "kind": "oracle", "cores": int(os.environ.get("OMP_NUM_THREADS",
+                                                                      os.cpu_count() or 1)),
+                        "sample": f"one pseudo-time iteration (5 stages) of the same step, "
+                                  f"{t_o:.1f} s"}
+        del o
+    rows["f4_dual_time"] = du
+
+    # Far-field noise.
+    r_of_j = np.hypot(xyz[1, 0, :, 0], xyz[2, 0, :, 0])
+    x_of_i = xyz[0, 0, 0, :]
+    js = int(np.argmin(np.abs(r_of_j - 1.5)))
+    i1, i2 = int(np.argmin(np.abs(x_of_i - 2.0))), int(np.argmin(np.abs(x_of_i - 6.0)))
+    src = np.array([0.5 * (x_of_i[i1] + x_of_i[i2]), 0.0, 0.0])
+    M, T, A = 256, 4.0, 1e-4
+    omega, dtau = 2 * math.pi / T, T / 32
+    rho0, c0, p0, gam = p.rho_inf, 1.0, p.p_inf, p.gamma
+    f = FWH(ctx, xyz, i1, i2, js, caps=3, capacity=M, dtau=dtau)
+    X = torch.from_numpy(xyz).cuda()
+    d = X - torch.tensor(src, dtype=torch.float64, device="cuda").view(3, 1, 1, 1)
+    R = torch.sqrt((d * d).sum(0))
+    gq = torch.empty_like(g)
+    for m in range(M):
+        tr = m * dtau - R / c0
+        fv = A * torch.sin(omega * tr)
+        fd = A * omega * torch.cos(omega * tr)
+        ur = fv / (4 * math.pi * R * R) + fd / (4 * math.pi * R * c0)
+        pp = rho0 * fd / (4 * math.pi * R)
+        rho = rho0 + pp / c0 ** 2
+        u = ur * d / R
+        gq[0] = rho
+        gq[1:4] = rho * u
+        gq[4] = (p0 + pp) / (gam - 1.0) + 0.5 * rho * (u * u).sum(0)
+        f.sample(gq)
+    del X, d, R
+    D = 30.0
+    ang = np.linspace(0.0, math.pi, 64)
+    obs = src[None, :] + D * np.stack([np.cos(ang), np.sin(ang), 0 * ang], axis=1)
+    times = np.linspace(38.0, 54.0, 256)
+    pr, _, skipped = f.pressure(obs, times, c0, p0)   # also forms the sources once
+    walls = []
+    for _ in range(3):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        pr, _, skipped = f.pressure(obs, times, c0, p0)
+        walls.append(time.perf_counter() - t0)
+    t_f = median(walls)
+    terms = len(obs) * len(times) * f.ns
+    tf = FWH_FLOP_PER_TERM * terms / t_f / 1e12
+    fw = {"workload": f"jet 256x128x128 control surface ({f.ns} nodes), {M} samples, "
+                      f"{len(obs)} observers x {len(times)} times",
+          "ms_per_call": round(t_f * 1e3, 3), "skipped_terms": int(skipped),
+          "value": round(terms / t_f / 1e9, 3), "unit": "Gterm/s",
+          "roofline": {"bound": "alu", "achieved": round(tf, 3),
+                       "peak": FP64_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s",
+                       "frac": round(tf / FP64_VECTOR_PEAK_TFLOPS, 4),
+                       "kernel": "k_fwh_integrate", "flop_per_term": FWH_FLOP_PER_TERM}}
+    if cpu:
+        o = oracle.Oracle(p, xyz)
+        ids, y, nrm, dS = fwh.jet_surface(o.S, xyz, i1, i2, js)
+        del o
+        idt = torch.from_numpy(np.asarray(ids, dtype=np.int64)).cuda()
+        rho_s = np.empty((M, len(ids)))
+        u_s = np.empty((M, len(ids), 3))
+        p_s = np.empty((M, len(ids)))
+        Xs = torch.from_numpy(xyz.reshape(3, -1)).cuda()[:, idt]
+        ds = Xs - torch.tensor(src, dtype=torch.float64, device="cuda").view(3, 1)
+        Rs = torch.sqrt((ds * ds).sum(0))
+        for m in range(M):  # the same monopole samples at the surface nodes
+            tr = m * dtau - Rs / c0
+            fd = A * omega * torch.cos(omega * tr)
+            fv = A * torch.sin(omega * tr)
+            ur = fv / (4 * math.pi * Rs * Rs) + fd / (4 * math.pi * Rs * c0)
+            pp = rho0 * fd / (4 * math.pi * Rs)
+            rho_s[m] = (rho0 + pp / c0 ** 2).cpu().numpy()
+            u_s[m] = (ur * ds / Rs).T.cpu().numpy()
+            p_s[m] = (p0 + pp).cpu().numpy()
+        no, nt = 4, 16
+        t0 = time.perf_counter()
+        fwh.fwh_pressure(y, nrm, dS, rho_s, u_s, p_s, 0.0, dtau, rho0, c0, p0, obs[:no],
+                         times[:nt])
+        t_o = time.perf_counter() - t0
+        fw["oracle"] = {"value": round(no * nt * len(ids) / t_o / 1e9, 5), "unit": "Gterm/s",
+                        "kind": "oracle", "cores": 1,
+                        "sample": f"{no} observers x {nt} times (numpy), {t_o:.2f} s"}
+    f.close()
+    rows["f3_fwh"] = fw
+    ctx.close()
+    return rows
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -310,6 +515,10 @@ def main():
                     help="only train the closure network briefly (256x128x128 FP64 run filtered "
                          "onto 128x64x64) and time learned-closure steps of the 384x192x192 "
                          "mixed jet (for counter runs of the closure kernels), then exit")
+    ap.add_argument("--rows-only", action="store_true",
+                    help="only measure the statistics, far-field noise and dual-time rows on "
+                         "the 256x128x128 jet (with the oracle beside them unless "
+                         "--cpu-steps 0) and print one JSON line, then exit")
     ap.add_argument("--mixed-only", action="store_true",
                     help="only time the mixed-precision form of the jet workload and print its "
                          "figures (for counter runs of its kernels), then exit")
@@ -346,6 +555,9 @@ def main():
         print(json.dumps({"mesh_sweep": rows, "unit": "Mcell-RKstage/s", "steps": args.steps,
                           "warmup": args.warmup, "workload": "synthetic jet, CFL 0.5, Smagorinsky"}),
               flush=True)
+        return
+    if args.rows_only:
+        print(json.dumps({"rows": run_rows(torch, cpu=args.cpu_steps > 0)}), flush=True)
         return
     if args.closure_only:
         from paper_2212_12365_amd import closure
@@ -430,6 +642,8 @@ def main():
                      "algorithmic_bytes_per_launch": per_launch,
                      "kernel_source_hash": khash},
     }
+    if args.forms:
+        out["rows"] = run_rows(torch, cpu=args.cpu_steps > 0)
     if args.cpu_steps > 0:
         out["cpu_baseline"] = cpu_baseline(params, xyz, q, args.cpu_steps)
     print(json.dumps(out), flush=True)

@@ -16,9 +16,10 @@
 //    the sample history [m][5][ns];
 //  * les_fwh_pressure: the sources Q_n, L_i of every sample and their time derivatives
 //    (central differences, second-order one-sided at both ends), then one block per
-//    (observer, time): the block's threads take the surface nodes in a fixed strided order,
-//    interpolate the sources linearly at the node's retarded time, and the block sums the
-//    terms in a fixed tree order, so the result does not depend on scheduling.
+//    observer and group of observer times: the block's threads take the surface nodes in a
+//    fixed strided order, interpolate the sources linearly at each node's retarded time, and
+//    the block sums the terms of each time in a fixed tree order, so the result does not
+//    depend on scheduling.
 #include <hip/hip_runtime.h>
 
 #include <cmath>
@@ -152,8 +153,15 @@ __global__ void k_fwh_prepare(int ns, int M, double dtau, double p0,
   }
 }
 
-// One block per (observer a, time b): p'[a][b], the sum of the absolute terms (scale) and
-// the number of nodes whose retarded time lies outside the samples.
+// Observer times per block of the integration kernel.
+constexpr int kFwhTimes = 8;
+
+// One block per (observer a, group of kFwhTimes consecutive observer times): p'[a][b], the
+// sum of the absolute terms (scale) and the number of nodes whose retarded time lies outside
+// the samples, for each time b of the group. A node's distance, unit vector and the factors
+// 1/r, 1/(c0 r), 1/r^2 do not depend on the time, so each thread forms them once per node
+// and then takes the group's times; for every (a, b) the nodes are summed in the same
+// strided order and the same tree as with one block per (a, b).
 __global__ void __launch_bounds__(kFwhBlock)
     k_fwh_integrate(int ns, int M, double tau0, double dtau, double c0,
                     const double* __restrict__ geo, const double* __restrict__ src,
@@ -161,49 +169,67 @@ __global__ void __launch_bounds__(kFwhBlock)
                     int nt, double* __restrict__ pout, double* __restrict__ scale,
                     double* __restrict__ skipped) {
   __shared__ double red[3][kFwhBlock];
-  const int a = blockIdx.x / nt, b = blockIdx.x % nt;
-  const double x = obs[3 * a], y = obs[3 * a + 1], z = obs[3 * a + 2], t = times[b];
-  double sum = 0.0, abs_sum = 0.0, skip = 0.0;
+  const int ngroups = (nt + kFwhTimes - 1) / kFwhTimes;
+  const int a = blockIdx.x / ngroups, b0 = (blockIdx.x % ngroups) * kFwhTimes;
+  const int nb = nt - b0 < kFwhTimes ? nt - b0 : kFwhTimes;
+  const double x = obs[3 * a], y = obs[3 * a + 1], z = obs[3 * a + 2];
+  double tb[kFwhTimes], sum[kFwhTimes], abs_sum[kFwhTimes], skip[kFwhTimes];
+#pragma unroll
+  for (int u = 0; u < kFwhTimes; ++u) {
+    tb[u] = u < nb ? times[b0 + u] : 0.0;
+    sum[u] = abs_sum[u] = skip[u] = 0.0;
+  }
   for (int s = threadIdx.x; s < ns; s += kFwhBlock) {
     const double dx = x - geo[s], dy = y - geo[ns + s], dz = z - geo[2 * ns + s];
     const double r = sqrt(dx * dx + dy * dy + dz * dz);
-    const double rh[3] = {dx / r, dy / r, dz / r};
-    const double sm = (t - r / c0 - tau0) / dtau;
-    int m = (int)floor(sm);
-    bool ok = m >= 0 && m + 1 <= M - 1;
-    if (m == M - 1 && sm == (double)(M - 1)) {  // exactly on the last sample
-      m = M - 2;
-      ok = true;
+    const double rh0 = dx / r, rh1 = dy / r, rh2 = dz / r;
+    const double rc = r / c0;
+    const double ir = 1.0 / r, icr = 1.0 / (c0 * r), ir2 = 1.0 / (r * r);
+    const double area = geo[6 * ns + s];
+#pragma unroll
+    for (int u = 0; u < kFwhTimes; ++u) {
+      if (u >= nb) break;
+      const double sm = (tb[u] - rc - tau0) / dtau;
+      int m = (int)floor(sm);
+      bool ok = m >= 0 && m + 1 <= M - 1;
+      if (m == M - 1 && sm == (double)(M - 1)) {  // exactly on the last sample
+        m = M - 2;
+        ok = true;
+      }
+      if (!ok) {
+        skip[u] += 1.0;
+        continue;
+      }
+      const double w = sm - m;
+      const double* s0 = src + (size_t)m * 7 * ns;
+      const double* s1 = s0 + 7 * ns;
+      auto at = [&](int c) { return (1.0 - w) * s0[c * ns + s] + w * s1[c * ns + s]; };
+      const double qd = at(0);
+      const double lr = at(1) * rh0 + at(2) * rh1 + at(3) * rh2;
+      const double ldr = at(4) * rh0 + at(5) * rh1 + at(6) * rh2;
+      const double term = area * (qd * ir + ldr * icr + lr * ir2);
+      sum[u] += term;
+      abs_sum[u] += fabs(term);
     }
-    if (!ok) {
-      skip += 1.0;
-      continue;
-    }
-    const double w = sm - m;
-    const double* s0 = src + (size_t)m * 7 * ns;
-    const double* s1 = s0 + 7 * ns;
-    auto at = [&](int c) { return (1.0 - w) * s0[c * ns + s] + w * s1[c * ns + s]; };
-    const double qd = at(0);
-    const double lr = at(1) * rh[0] + at(2) * rh[1] + at(3) * rh[2];
-    const double ldr = at(4) * rh[0] + at(5) * rh[1] + at(6) * rh[2];
-    const double term = geo[6 * ns + s] * (qd / r + ldr / (c0 * r) + lr / (r * r));
-    sum += term;
-    abs_sum += fabs(term);
   }
-  red[0][threadIdx.x] = sum;
-  red[1][threadIdx.x] = abs_sum;
-  red[2][threadIdx.x] = skip;
-  __syncthreads();
-  for (int h = kFwhBlock / 2; h > 0; h >>= 1) {
-    if ((int)threadIdx.x < h)
-      for (int c = 0; c < 3; ++c) red[c][threadIdx.x] += red[c][threadIdx.x + h];
+  const double k = 1.0 / (4.0 * M_PI);
+  for (int u = 0; u < nb; ++u) {
+    red[0][threadIdx.x] = sum[u];
+    red[1][threadIdx.x] = abs_sum[u];
+    red[2][threadIdx.x] = skip[u];
     __syncthreads();
-  }
-  if (threadIdx.x == 0) {
-    const double k = 1.0 / (4.0 * M_PI);
-    pout[(size_t)a * nt + b] = red[0][0] * k;
-    if (scale) scale[(size_t)a * nt + b] = red[1][0] * k;
-    skipped[(size_t)a * nt + b] = red[2][0];
+    for (int h = kFwhBlock / 2; h > 0; h >>= 1) {
+      if ((int)threadIdx.x < h)
+        for (int c = 0; c < 3; ++c) red[c][threadIdx.x] += red[c][threadIdx.x + h];
+      __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+      const size_t o = (size_t)a * nt + b0 + u;
+      pout[o] = red[0][0] * k;
+      if (scale) scale[o] = red[1][0] * k;
+      skipped[o] = red[2][0];
+    }
+    __syncthreads();
   }
 }
 
@@ -351,7 +377,9 @@ int les_fwh_pressure(les_fwh* f, const double* observers, int no, const double* 
   double* d_skip = d_t + nt;
   FHIP(f, hipMemcpyAsync(d_o, observers, sizeof(double) * 3 * no, hipMemcpyHostToDevice, s));
   FHIP(f, hipMemcpyAsync(d_t, times, sizeof(double) * nt, hipMemcpyHostToDevice, s));
-  hipLaunchKernelGGL(k_fwh_integrate, dim3(no * nt), dim3(kFwhBlock), 0, s, ns, M, tau0,
+  const long long blocks = (long long)no * ((nt + kFwhTimes - 1) / kFwhTimes);
+  if (blocks > 0x7fffffffLL) return ffail(f, LES_EINVAL, "too many observers x times");
+  hipLaunchKernelGGL(k_fwh_integrate, dim3((unsigned)blocks), dim3(kFwhBlock), 0, s, ns, M, tau0,
                      f->dtau, c0, f->geo, f->src, d_o, no, d_t, nt, p_out, scale_out, d_skip);
   if (hipGetLastError() != hipSuccess) return ffail(f, LES_EHIP, "integration kernel");
   std::vector<double> sk((size_t)no * nt);
