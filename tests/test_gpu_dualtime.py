@@ -60,3 +60,34 @@ def test_dual_time_steps_match_oracle(torch, name, precision):
         assert np.all(np.abs(r - rr) <= rtol * rr[:, :1])
         assert r[0, -1] < r[0, 0]
     ctx.close()
+
+
+def test_dual_time_two_steps_equal_one_plus_one_and_edges(torch):
+    """Two physical steps in one call equal one call and a second with the history passed
+    back, bit for bit (the same kernels in the same order); a call of zero steps leaves the
+    state alone; bad arguments are refused."""
+    print("[gpu] dual time: chained calls and edges", flush=True)
+    from paper_2212_12365_amd.lesmi import Context, LesError, LES_EINVAL
+    p, xyz, q = case("jet_small")
+    o = oracle.Oracle(p, xyz)
+    q = o.apply_bc(q)
+    dt = 4.0 * o.dt(q, 0.5)
+    ctx = Context(p, xyz)
+    a = torch.from_numpy(q).cuda()
+    b = a.clone()
+    ra = ctx.dual_step(a, 2, dt, 3, 1.0, q_prev=None)   # backward Euler, then BDF2
+    rb1 = ctx.dual_step(b, 1, dt, 3, 1.0, q_prev=None)  # backward Euler: Q^1
+    hist = torch.from_numpy(q).cuda()                   # Q^0, the history of the next step
+    rb2 = ctx.dual_step(b, 1, dt, 3, 1.0, q_prev=hist)  # BDF2: Q^2; hist becomes Q^1
+    assert torch.equal(a, b), (a - b).abs().max()
+    np.testing.assert_array_equal(ra[0], rb1[0])
+    np.testing.assert_array_equal(ra[1], rb2[0])
+    before = a.clone()
+    r0 = ctx.dual_step(a, 0, dt, 3, 1.0)
+    assert r0.size == 0 and torch.equal(a, before)
+    for args in ((1, 0.0, 3, 1.0), (1, dt, 0, 1.0), (1, dt, 3, 0.0), (-1, dt, 3, 1.0)):
+        with pytest.raises(LesError) as e:
+            ctx.dual_step(a, *args)
+        assert e.value.code == LES_EINVAL
+    assert torch.equal(a, before)
+    ctx.close()

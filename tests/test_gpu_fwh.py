@@ -112,3 +112,78 @@ def test_fwh_monopole_gpu_against_oracle(torch):
     assert err < 4e-2
     f.close()
     ctx.close()
+
+
+def test_fwh_ragged_groups_skipped_times_and_errors(torch):
+    """Observer times that are not a multiple of the kernel's group of 8, a single observer,
+    and times whose retarded times fall partly outside the samples: the GPU pressure against
+    the oracle's within the same rounding bound, and the skipped counts equal. Then the error
+    paths: a full history, too few samples, a bad surface, a periodic box."""
+    print("[gpu] Ffowcs Williams-Hawkings ragged groups and edges", flush=True)
+    from paper_2212_12365_amd.lesmi import FWH, Context, LesError, LES_ESTATE, LES_EINVAL
+    n = (48, 32, 16)
+    xyz, _ = jet_grid(n)
+    p = sy.jet_params(n)
+    rho0, c0, p0 = p.rho_inf, 1.0, p.p_inf
+    r_of_j = np.hypot(xyz[1, 0, :, 0], xyz[2, 0, :, 0])
+    x_of_i = xyz[0, 0, 0, :]
+    js = int(np.argmin(np.abs(r_of_j - 1.5)))
+    i1, i2 = int(np.argmin(np.abs(x_of_i - 2.0))), int(np.argmin(np.abs(x_of_i - 6.0)))
+    src = np.array([0.5 * (x_of_i[i1] + x_of_i[i2]), 0.0, 0.0])
+    A, T = 1e-4, 4.0
+    omega, dtau, M = 2 * math.pi / T, T / 16, 40
+    o = oracle.Oracle(p, xyz)
+    ids, y, nrm, dS = fwh.jet_surface(o.S, xyz, i1, i2, js, caps=(True, False))
+    ctx = Context(p, xyz)
+    f = FWH(ctx, xyz, i1, i2, js, caps=1, capacity=M, dtau=dtau)
+    assert f.ns == len(ids)
+    g = torch.empty((5,) + p.shape, dtype=torch.float64, device="cuda")
+    rho = np.empty((M, len(ids)))
+    u = np.empty((M, len(ids), 3))
+    pr = np.empty((M, len(ids)))
+    with pytest.raises(LesError) as e:
+        f.pressure(src[None, :] + 10.0, [12.0], c0, p0)
+    assert e.value.code == LES_ESTATE  # fewer than three samples
+    for m in range(M):
+        q = monopole_state(xyz, src, A, omega, m * dtau, p.gamma, rho0, c0, p0)
+        rho[m], u[m], pr[m] = fwh.sample_state(q, ids, p.gamma)
+        g.copy_(torch.from_numpy(q))
+        f.sample(g)
+    with pytest.raises(LesError) as e:
+        f.sample(g)
+    assert e.value.code == LES_ESTATE  # the history is full
+    D = 12.0
+    for obs in (np.array([[0.0, 1.0, 0.3]]), np.array([[1, 0, 0], [0, 1, 0], [-1, 0.5, 0.2]])):
+        obs = src[None, :] + D * obs / np.linalg.norm(obs, axis=1)[:, None]
+        # from before the first retarded time to after the last: skipped terms at both ends
+        times = np.linspace(D / c0 - 4.0, D / c0 + M * dtau + 3.0, 13)
+        got, scale, skipped = f.pressure(obs, times, c0, p0)
+        ref, ref_scale, ref_skipped = fwh.fwh_pressure(y, nrm, dS, rho, u, pr, 0.0, dtau, rho0,
+                                                       c0, p0, obs, times)
+        print("skipped", skipped, "oracle", ref_skipped)
+        assert skipped == ref_skipped and skipped > 0
+        Q, L = fwh.sources(rho, u, pr, nrm, p0)
+        qmax = np.abs(Q).max(axis=0)
+        lmax = np.sqrt(np.sum(L * L, axis=2)).max(axis=0)
+        for a, x in enumerate(obs):
+            r = np.sqrt(np.sum((x[None, :] - y) ** 2, axis=1))
+            bound = 1e-14 * np.sum(dS * (qmax / (dtau * r) + lmax / (dtau * c0 * r) +
+                                         lmax / (r * r))) / (4 * math.pi)
+            assert np.all(np.abs(got.cpu().numpy()[a] - ref[a]) <= bound)
+        np.testing.assert_allclose(scale.cpu().numpy(), ref_scale, rtol=1e-12, atol=0)
+    f.reset()
+    assert f.samples() == 0
+    f.sample(g)
+    assert f.samples() == 1
+    f.close()
+    for bad in ((i1, i1, js), (i1, i2, 0), (i1, n[0], js), (i1, i2, n[1])):
+        with pytest.raises(LesError) as e:
+            FWH(ctx, xyz, *bad, caps=3, capacity=8, dtau=dtau)
+        assert e.value.code == LES_EINVAL
+    ctx.close()
+    xb, sh = sy.skewed_periodic_grid((8, 8, 8))
+    cb = Context(sy.box_params((8, 8, 8), sh), xb)
+    with pytest.raises(LesError) as e:  # no jet surface on a periodic box
+        FWH(cb, xb, 1, 4, 2, caps=3, capacity=8, dtau=dtau)
+    assert e.value.code == LES_EINVAL
+    cb.close()
