@@ -147,7 +147,8 @@ int les_step(les_ctx* ctx, double* q, int nsteps, double cfl, double dt_fixed,
  * on return, so that calls chain. res_out (HOST [nsteps * subiters], may be NULL) receives
  * the r.m.s. over updated nodes of the unsteady mass residual at the start of every
  * iteration. The first call allocates four state-sized buffers; synchronises once, at the
- * end. Errors as les_step. */
+ * end. q_prev must not alias q. LES_EINVAL for nsteps < 0, subiters < 1, dt or cfl_tau not
+ * positive, or nsteps * subiters above 2^24; otherwise errors as les_step. */
 int les_dual_step(les_ctx* ctx, double* q, double* q_prev, int nsteps, double dt,
                   int subiters, double cfl_tau, double* res_out, void* stream);
 

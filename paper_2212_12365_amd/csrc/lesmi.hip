@@ -860,6 +860,9 @@ int les_step(les_ctx* c, double* q, int nsteps, double cfl, double dt_fixed, dou
   return LES_OK;
 }
 
+// Largest residual history of one les_dual_step call (nsteps x subiters values).
+constexpr long long kMaxDualResiduals = 1LL << 24;
+
 int les_dual_step(les_ctx* c, double* q, double* q_prev, int nsteps, double dt, int subiters,
                   double cfl_tau, double* res_out, void* stream) {
   if (!c || !q || nsteps < 0 || subiters < 1 || !(dt > 0.0) || !(cfl_tau > 0.0))
@@ -872,6 +875,7 @@ int les_dual_step(les_ctx* c, double* q, double* q_prev, int nsteps, double dt, 
                       dev_alloc(c, &c->dual_rhs, 5 * N) || dev_alloc(c, &c->dual_dtau, N)))
     return LES_ENOMEM;
   const long long nres = (long long)nsteps * subiters;
+  if (nres > kMaxDualResiduals) return fail(c, LES_EINVAL, "nsteps x subiters too large");
   if (nres > c->dual_res_cap) {
     if (c->dual_res) (void)hipFree(c->dual_res);
     c->dual_res = nullptr;
