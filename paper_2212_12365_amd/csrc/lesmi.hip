@@ -424,13 +424,23 @@ __global__ void __launch_bounds__(256) k_dual_update(DualArgs A) {
   if (threadIdx.x == 0) A.part[blockIdx.x] = red[0];
 }
 
-// out[0] = sqrt(sum of the block sums, in block order / nupd).
-__global__ void k_dual_res_final(const double* __restrict__ part, int nparts, double nupd,
-                                 double* __restrict__ out) {
-  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+// out[0] = sqrt(sum of the block sums / nupd), in one block of 256 threads and a fixed
+// order: thread t sums the partials t*per .. (t+1)*per - 1 in turn, then a tree over the
+// threads.
+__global__ void __launch_bounds__(256) k_dual_res_final(const double* __restrict__ part,
+                                                        int nparts, double nupd,
+                                                        double* __restrict__ out) {
+  __shared__ double red[256];
+  const int t = threadIdx.x, per = (nparts + 255) / 256;
   double s = 0.0;
-  for (int b = 0; b < nparts; ++b) s += part[b];
-  out[0] = sqrt(s / nupd);
+  for (int b = t * per; b < (t + 1) * per && b < nparts; ++b) s += part[b];
+  red[t] = s;
+  __syncthreads();
+  for (int h = 128; h > 0; h >>= 1) {
+    if (t < h) red[t] += red[t + h];
+    __syncthreads();
+  }
+  if (t == 0) out[0] = sqrt(red[0] / nupd);
 }
 
 // ---------------------------------------------------------------------------------------
@@ -920,7 +930,7 @@ int les_dual_step(les_ctx* c, double* q, double* q_prev, int nsteps, double dt, 
         A.chunk = chunk;
         hipLaunchKernelGGL(k_dual_update, dim3(nparts), dim3(256), 0, s, A);
         if (l == 0)
-          hipLaunchKernelGGL(k_dual_res_final, dim3(1), dim3(1), 0, s, c->d_partial, nparts,
+          hipLaunchKernelGGL(k_dual_res_final, dim3(1), dim3(256), 0, s, c->d_partial, nparts,
                              (double)c->n_updated, c->dual_res + (size_t)n * subiters + it);
         rc = run_bc(c, outb, s);
         if (rc) return rc;
