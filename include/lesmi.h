@@ -366,7 +366,9 @@ typedef struct les_fwh les_fwh;
  * given to les_init_grid). capacity >= 3: samples the history holds (5 doubles per node and
  * sample, plus 7 for the sources). dtau > 0: the sampling interval, which the caller keeps
  * uniform (for instance a sample every m steps of fixed dt). Allocates; synchronous.
- * LES_EINVAL for a periodic box or indices outside the grid. */
+ * LES_EINVAL for a periodic box or indices outside the grid (*out is then NULL). If a later
+ * step fails (LES_ENOMEM, LES_EHIP), *out holds the object so that les_fwh_last_error can
+ * say why; destroy it. ctx must outlive the surface. */
 int les_fwh_create(les_ctx* ctx, const double* xyz, int i1, int i2, int js, int caps,
                    int capacity, double dtau, les_fwh** out);
 /* Number of surface nodes, and of samples taken. */
@@ -383,8 +385,9 @@ int les_fwh_reset(les_fwh* f);
  * [no][nt]; scale_out DEVICE [no][nt] or NULL receives the sum of the absolute values of the
  * terms; skipped HOST or NULL the number of (observer, time, node) triples whose retarded
  * time fell outside [tau0, tau0 + (samples - 1) dtau] and were left out. Sample m is taken
- * to be at tau0 + m dtau. Needs 3 samples or more (LES_ESTATE). Synchronises the stream;
- * may allocate a small observer buffer. */
+ * to be at tau0 + m dtau. Needs 3 samples or more (LES_ESTATE); LES_EINVAL for no or nt
+ * below 1, c0 not positive, or no * nt above about 2^28. Synchronises the stream; may
+ * allocate a small observer buffer. */
 int les_fwh_pressure(les_fwh* f, const double* observers, int no, const double* times, int nt,
                      double c0, double p0, double tau0, double* p_out, double* scale_out,
                      long long* skipped, void* stream);

@@ -43,9 +43,9 @@ struct les_fwh {
   double* src = nullptr;   // [capacity][7][ns] dQ_n/dtau, L (3), dL/dtau (3)
   int src_count = -1;      // samples the sources were formed from
   double src_p0 = 0.0;
-  double* d_obs = nullptr;  // observer positions and times of the last call
-  int obs_cap = 0;
-  double* d_red = nullptr;  // per-(observer, time) skipped counts (as doubles)
+  double* d_obs = nullptr;  // observer positions, times and per-(observer, time) skipped
+                            // counts (as doubles) of the last call
+  long long obs_cap = 0;
   std::string err;
 };
 
@@ -234,7 +234,7 @@ __global__ void __launch_bounds__(kFwhBlock)
 }
 
 void free_fwh(les_fwh* f) {
-  void* ptrs[] = {f->ids, f->geo, f->hist, f->src, f->d_obs, f->d_red};
+  void* ptrs[] = {f->ids, f->geo, f->hist, f->src, f->d_obs};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
 }
@@ -365,10 +365,12 @@ int les_fwh_pressure(les_fwh* f, const double* observers, int no, const double* 
     f->src_count = M;
     f->src_p0 = p0;
   }
-  const int need = 3 * no + nt + no * nt;
+  const long long need = 3LL * no + nt + (long long)no * nt;
+  if (need > (1LL << 28)) return ffail(f, LES_EINVAL, "too many observers x times");
   if (need > f->obs_cap) {
     if (f->d_obs) (void)hipFree(f->d_obs);
     f->d_obs = nullptr;
+    f->obs_cap = 0;
     FHIP(f, hipMalloc((void**)&f->d_obs, sizeof(double) * need));
     f->obs_cap = need;
   }
