@@ -319,6 +319,8 @@ def event_time(torch, fn, reps):
 def run_rows(torch, cpu=True):
     """The rows beyond the explicit step on the 256 x 128 x 128 jet, each timed on the GPU and
     set against its roofline, with the oracle timed beside it on a bounded sample:
+    * grid metrics: les_init_grid (once per run);
+    * diagnostics: les_diagnostics (HBM-bound: 48 B per node), with its return to the host;
     * running statistics: one les_stats_accumulate sample (HBM-bound: 200 B per node), and
       the azimuthal reduction;
     * far-field noise: les_fwh_pressure on a control surface around the jet (x from 2 to 6,
@@ -335,11 +337,55 @@ def run_rows(torch, cpu=True):
     from paper_2212_12365_amd.lesmi import FWH, Context
     p, xyz, q = sy.make_case("jet", JET_GRID, seed=0)
     N = p.ni * p.nj * p.nk
+    Context(p, xyz).close()  # warm-up (module load)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
     ctx = Context(p, xyz)
+    torch.cuda.synchronize()
+    t_init = time.perf_counter() - t0
     g = torch.from_numpy(q).cuda()
     ctx.apply_bc(g)
     upd = ctx.updated_nodes()
     rows = {}
+
+    # Grid metrics (once per run): les_init_grid, including the upload of the coordinates.
+    mt = {"workload": "jet 256x128x128 grid: metrics, J^-1, J and boundary normals",
+          "ms_per_init": round(t_init * 1e3, 2)}
+    if cpu:
+        t0 = time.perf_counter()
+        oracle.Oracle(p, xyz)
+        t_o = time.perf_counter() - t0
+        mt["oracle"] = {"ms_per_init": round(t_o * 1e3, 1), "kind": "oracle",
+                        "cores": int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1)),
+                        "sample": "the oracle's metrics and J^-1 of the same grid"}
+    rows["a1_metrics"] = mt
+
+    # Diagnostics (volume-weighted kinetic energy and conserved totals, fixed-order sums):
+    # q and J^-1 read once, 48 B per node; the call returns to the host.
+    walls = []
+    for _ in range(10):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        ctx.diagnostics(g)
+        walls.append(time.perf_counter() - t0)
+    t_dg = median(walls)
+    dg = {"workload": "jet 256x128x128 FP64 state", "us_per_call": round(t_dg * 1e6, 1),
+          "value": round(N / t_dg / 1e6, 1), "unit": "Mnode/s",
+          "roofline": {"bound": "hbm", "achieved": round(48 * N / t_dg / 1e9, 1),
+                       "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                       "frac": round(48 * N / t_dg / 1e9 / HBM_PEAK_GBS, 4),
+                       "bytes_per_node": 48, "note": "wall time of the call, with its return"}}
+    if cpu:
+        o = oracle.Oracle(p, xyz)
+        t0 = time.perf_counter()
+        for _ in range(3):
+            o.diagnostics(q)
+        t_o = (time.perf_counter() - t0) / 3
+        del o
+        dg["oracle"] = {"value": round(N / t_o / 1e6, 1), "unit": "Mnode/s", "kind": "oracle",
+                        "cores": int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1)),
+                        "sample": f"3 calls on the same state, {t_o * 1e3:.1f} ms each"}
+    rows["a12_diagnostics"] = dg
 
     # Running statistics.
     ctx.stats_reset()

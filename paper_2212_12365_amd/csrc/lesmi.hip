@@ -246,14 +246,26 @@ __global__ void k_diag_partial(Dims D, const double* __restrict__ q,
   if (threadIdx.x == 0) part[(long long)blockIdx.x * 7 + 6] = red[0][0];
 }
 
-__global__ void k_diag_final(const double* __restrict__ part, int nparts,
-                             double* __restrict__ out) {
-  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+// Sums of the block partials in one block of 256 threads and a fixed order: thread t sums
+// the partials t*per .. (t+1)*per - 1 in turn, then a tree over the threads.
+__global__ void __launch_bounds__(256) k_diag_final(const double* __restrict__ part,
+                                                    int nparts, double* __restrict__ out) {
+  __shared__ double red[7][256];
+  const int t = threadIdx.x, per = (nparts + 255) / 256;
   double s[7] = {0, 0, 0, 0, 0, 0, 0};
-  for (int b = 0; b < nparts; ++b)
+  for (int b = t * per; b < (t + 1) * per && b < nparts; ++b)
     for (int c = 0; c < 7; ++c) s[c] += part[(long long)b * 7 + c];
-  out[0] = s[0] / s[6];
-  for (int c = 0; c < 5; ++c) out[1 + c] = s[1 + c];
+  for (int c = 0; c < 7; ++c) red[c][t] = s[c];
+  __syncthreads();
+  for (int h = 128; h > 0; h >>= 1) {
+    if (t < h)
+      for (int c = 0; c < 7; ++c) red[c][t] += red[c][t + h];
+    __syncthreads();
+  }
+  if (t == 0) {
+    out[0] = red[0][0] / red[6][0];
+    for (int c = 0; c < 5; ++c) out[1 + c] = red[1 + c][0];
+  }
 }
 
 // Running statistics of the primitive variables (rho, u, v, w, p) at every node: one
@@ -331,16 +343,31 @@ __global__ void k_rhs_norm_partial(Dims D, const double* __restrict__ rhs,
   if (threadIdx.x < 2) part[(long long)blockIdx.x * 2 + threadIdx.x] = red[threadIdx.x][0];
 }
 
-__global__ void k_rhs_norm_final(const double* __restrict__ part, int nparts, double nupd,
-                                 double* __restrict__ out) {
-  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+// The same one-block fixed-order reduction of (sum of squares, maximum) partials.
+__global__ void __launch_bounds__(256) k_rhs_norm_final(const double* __restrict__ part,
+                                                        int nparts, double nupd,
+                                                        double* __restrict__ out) {
+  __shared__ double red[2][256];
+  const int t = threadIdx.x, per = (nparts + 255) / 256;
   double s2 = 0.0, mx = 0.0;
-  for (int b = 0; b < nparts; ++b) {
+  for (int b = t * per; b < (t + 1) * per && b < nparts; ++b) {
     s2 += part[2 * b];
     mx = fmax(mx, part[2 * b + 1]);
   }
-  out[0] = sqrt(s2 / nupd);
-  out[1] = mx;
+  red[0][t] = s2;
+  red[1][t] = mx;
+  __syncthreads();
+  for (int h = 128; h > 0; h >>= 1) {
+    if (t < h) {
+      red[0][t] += red[0][t + h];
+      red[1][t] = fmax(red[1][t], red[1][t + h]);
+    }
+    __syncthreads();
+  }
+  if (t == 0) {
+    out[0] = sqrt(red[0][0] / nupd);
+    out[1] = red[1][0];
+  }
 }
 
 // ---------------------------------------------------------------------------------------
@@ -964,7 +991,7 @@ int les_diagnostics(les_ctx* c, const double* q, double* out, void* stream) {
   int nparts = (int)((D.N + chunk - 1) / chunk);
   hipLaunchKernelGGL(k_diag_partial, dim3(nparts), dim3(kBlock), 0, s, D, q, c->jinv,
                      c->d_partial, chunk);
-  hipLaunchKernelGGL(k_diag_final, dim3(1), dim3(1), 0, s, c->d_partial, nparts, c->d_diag);
+  hipLaunchKernelGGL(k_diag_final, dim3(1), dim3(256), 0, s, c->d_partial, nparts, c->d_diag);
   int rc = launch_check(c, "diagnostics");
   if (rc) return rc;
   HIP_TRY(c, hipMemcpyAsync(out, c->d_diag, 6 * sizeof(double), hipMemcpyDeviceToHost, s));
@@ -984,7 +1011,7 @@ int les_residual_norms(les_ctx* c, const double* q, double* out, void* stream) {
   const int nparts = (int)((D.N + chunk - 1) / chunk);
   hipLaunchKernelGGL(k_rhs_norm_partial, dim3(nparts), dim3(kBlock), 0, s, D, c->qb,
                      c->d_partial, chunk);
-  hipLaunchKernelGGL(k_rhs_norm_final, dim3(1), dim3(1), 0, s, c->d_partial, nparts,
+  hipLaunchKernelGGL(k_rhs_norm_final, dim3(1), dim3(256), 0, s, c->d_partial, nparts,
                      (double)c->n_updated, c->d_diag);
   rc = launch_check(c, "residual norms");
   if (rc) return rc;
