@@ -169,8 +169,14 @@ __global__ void __launch_bounds__(kFwhBlock)
                     int nt, double* __restrict__ pout, double* __restrict__ scale,
                     double* __restrict__ skipped) {
   __shared__ double red[3][kFwhBlock];
-  const int ngroups = (nt + kFwhTimes - 1) / kFwhTimes;
-  const int a = blockIdx.x / ngroups, b0 = (blockIdx.x % ngroups) * kFwhTimes;
+  // Work item of the block: blocks are dealt to the 8 XCDs in turn (block b on XCD b % 8), so
+  // each XCD takes a contiguous run of items; consecutive items share a group of observer
+  // times (observer fastest), so the blocks that run together on one XCD gather the sources
+  // of nearby retarded samples through its L2.
+  const int nblk = gridDim.x, full = nblk / 8 * 8;
+  const int item = (int)blockIdx.x >= full ? (int)blockIdx.x
+                                           : (blockIdx.x % 8) * (full / 8) + blockIdx.x / 8;
+  const int a = item % no, b0 = (item / no) * kFwhTimes;
   const int nb = nt - b0 < kFwhTimes ? nt - b0 : kFwhTimes;
   const double x = obs[3 * a], y = obs[3 * a + 1], z = obs[3 * a + 2];
   double tb[kFwhTimes], sum[kFwhTimes], abs_sum[kFwhTimes], skip[kFwhTimes];
