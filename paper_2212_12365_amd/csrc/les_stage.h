@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include "les_common.h"
+#include "les_mlp.h"
 
 namespace lesmi {
 
@@ -51,6 +52,12 @@ struct StageArgs {
   float* feat;
   float* fscale;
   float* fsmag;
+  // Learned closure evaluated inside the node kernel (mlp_fused != 0): the network's
+  // coefficient replaces the Smagorinsky coefficient in the eddy-viscosity record, with no
+  // inputs written out; fallback nodes are counted into *mlp_fallback (may be null).
+  int mlp_fused;
+  MlpNet mlp;
+  unsigned* mlp_fallback;
 };
 
 constexpr int kNumTiles = 10;

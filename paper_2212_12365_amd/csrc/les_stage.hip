@@ -16,6 +16,7 @@
 
 #include "les_common.h"
 #include "les_mlp.h"
+#include "les_mlp_infer.h"
 #include "les_stage.h"
 
 namespace lesmi {
@@ -96,11 +97,14 @@ __device__ __forceinline__ NodeState<R> node_state(const StageArgs& A, unsigned 
 // LDS: nl[f * kNodeTileN + npos +- 1] along xi and +- kNodeTileX along eta (f = u, v, w, p).
 constexpr int kNodeTileX = 66, kNodeTileY = 6, kNodeTileN = kNodeTileX * kNodeTileY;
 
+// With mlp_in non-null the eddy-viscosity record is left to the caller and the closure's
+// inputs come back in mlp_in[0..5], its scale rho Delta^2 |S| in mlp_in[6] (as FP32, the
+// values the inference kernel would read).
 template <typename R, bool kQueue>
 __device__ __forceinline__ void node_record(const StageArgs& A, int i, int j, int k,
                                             const Prim& zm, const Prim& z0, const Prim& zp,
                                             const R* nl = nullptr, int npos = 0,
-                                            double* rdt = nullptr) {
+                                            double* rdt = nullptr, float* mlp_in = nullptr) {
   const Dims& D = A.D;
   const PhysT<R> P(A.P);
   const int N = (int)D.N;
@@ -182,7 +186,7 @@ __device__ __forceinline__ void node_record(const StageArgs& A, int i, int j, in
   R lb[3];
   scaled_radii<R>(l0, l1, l2, lb);
   R* __restrict__ r = records_of<R>(A);
-  r[kRecMut * N + o] = mut;
+  if (!mlp_in) r[kRecMut * N + o] = mut;
   r[(kRecLb + 0) * N + o] = lb[0];
   r[(kRecLb + 1) * N + o] = lb[1];
   r[(kRecLb + 2) * N + o] = lb[2];
@@ -193,6 +197,16 @@ __device__ __forceinline__ void node_record(const StageArgs& A, int i, int j, in
   r[(kRecDz + 1) * N + o] = du[2][1];
   r[(kRecDz + 2) * N + o] = du[2][2];
   r[(kRecDz + 3) * N + o] = dzT;
+  if (mlp_in) {  // inputs of the learned closure, kept in registers
+    R g[3][3], f[kMlpIn];
+    velocity_gradient<R>(sm, du, jinv, g);
+    const R smag = mlp_invariants<R>(g, f);
+#pragma unroll
+    for (int c = 0; c < kMlpIn; ++c) mlp_in[c] = (float)f[c];
+    const R dl = jinv > (R)0 ? cbrt(jinv) : (R)0;
+    mlp_in[kMlpIn] = (float)((R)s.rho * dl * dl * smag);
+    return;
+  }
   if (A.mut_out) A.mut_out[o] = (double)mut;
   if (A.feat || A.fscale || A.fsmag) {  // inputs of the learned closure
     R g[3][3], f[kMlpIn];
@@ -214,9 +228,19 @@ __device__ __forceinline__ void node_record(const StageArgs& A, int i, int j, in
 // so the centred xi and eta differences read the tile and each node's primitive variables
 // are formed about 1.5 times per plane. One-sided differences at the ends of a non-periodic
 // direction read global memory.
-template <typename R, bool kDt = false>
+// LDS of the learned closure evaluated in the node kernel: per-lane weight fragments, the
+// biases and output weights (b1, b2, w3, b3), and each wave's split h1 rows.
+struct NodeMlpLds {
+  bf16x8 F[kInferFrags * 64];
+  float bs[196];
+  __bf16 H[4][16 * HS];
+  __bf16 Hl[4][16 * HS];
+};
+
+template <typename R, bool kDt = false, bool kMlp = false>
 __device__ __forceinline__ void nodes_tile_block(const StageArgs& A, int bx, int by, int kbeg,
-                                                 int kend, R* Lp, int slot = 0) {
+                                                 int kend, R* Lp, int slot = 0,
+                                                 NodeMlpLds* ML = nullptr) {
   const Dims& D = A.D;
   const int ni = D.n[0], nj = D.n[1], nk = D.n[2], N = (int)D.N;
   const int tx = threadIdx.x, ty = threadIdx.y, tid = tx + 64 * ty;
@@ -249,6 +273,7 @@ __device__ __forceinline__ void nodes_tile_block(const StageArgs& A, int bx, int
   }
   const int o0 = i + ni * j;
   double rdt = INFINITY;  // this column's minimum of the time-step reduction
+  unsigned nfb = 0;       // closure nodes of this thread that fell back to C_s^2
   Prim zm{}, z0{};
   if (mine) {
     zm = load_prim(A.q, N, o0 + pl * (kbeg == 0 ? nk - 1 : kbeg - 1), A.P);
@@ -282,9 +307,43 @@ __device__ __forceinline__ void nodes_tile_block(const StageArgs& A, int bx, int
     // each plane instead of holding registers across the loop.
     int il = i, jl = j, ol = own;
     asm volatile("" : "+v"(il), "+v"(jl), "+v"(ol));
-    if (mine) node_record<R, true>(A, il, jl, k, zm, z0, zp, Lp, ol, kDt ? &rdt : nullptr);
+    if constexpr (kMlp) {
+      // The wave's 64 nodes of this plane (one row of the tile) are the 64 samples of one
+      // inference pass, in the order and arithmetic of the inference kernel; lanes without
+      // a node take part with zero inputs and write nothing.
+      float fin[kMlpIn + 1];
+#pragma unroll
+      for (int c = 0; c <= kMlpIn; ++c) fin[c] = 0.f;
+      if (mine)
+        node_record<R, true>(A, il, jl, k, zm, z0, zp, Lp, ol, kDt ? &rdt : nullptr, fin);
+      float x[kMlpIn];
+      const bool ok = mlp_input(A.mlp, fin, fin[kMlpIn], x);
+      const int lane = tx, g = lane >> 4, sl = lane & 15;
+      float zmine = 0.f;
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        float xs[kMlpIn];
+#pragma unroll
+        for (int c = 0; c < kMlpIn; ++c) xs[c] = __shfl(x[c], sl + 16 * t);
+        const float z = forward16_split_lds(ML->bs, ML->F, xs, lane, ML->H[ty], ML->Hl[ty]);
+        if (g == t) zmine = z;
+      }
+      if (mine) {
+        const float cc = ok ? softplus_f(zmine) : A.mlp.cs2;
+        nfb += ok ? 0u : 1u;
+        const double mu = (double)fin[kMlpIn] * (double)cc;
+        records_of<R>(A)[kRecMut * N + (il + ni * (jl + nj * k))] = (R)mu;
+      }
+    } else {
+      if (mine) node_record<R, true>(A, il, jl, k, zm, z0, zp, Lp, ol, kDt ? &rdt : nullptr);
+    }
     zm = z0;
     z0 = zp;
+  }
+  if constexpr (kMlp) {  // the wave's fallback count
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) nfb += __shfl_xor(nfb, o);
+    if (tx == 0 && nfb && A.mlp_fallback) atomicAdd(A.mlp_fallback, nfb);
   }
   if constexpr (kDt) {  // the block's minimum (the tile is free now)
 #pragma unroll
@@ -304,6 +363,30 @@ __global__ void __launch_bounds__(256) k_nodes_tile(StageArgs A, int kchunk) {
   const int kbeg = blockIdx.z * kchunk;
   nodes_tile_block<R, kDt>(A, blockIdx.x, blockIdx.y, kbeg, min(kbeg + kchunk, A.D.n[2]), Lp,
                            blockIdx.x + gridDim.x * (blockIdx.y + gridDim.y * blockIdx.z));
+}
+
+// The same with the learned closure evaluated for each plane's nodes (StageArgs.mlp_fused):
+// the block first lays the network's weight fragments into LDS.
+template <typename R, bool kDt = false>
+__global__ void __launch_bounds__(256) k_nodes_tile_mlp(StageArgs A, int kchunk) {
+  __shared__ R Lp[4 * kNodeTileN];
+  __shared__ NodeMlpLds ML;
+  const float* __restrict__ th = A.mlp.theta;
+  infer_frags_to_lds(th, ML.F, threadIdx.y, 4, threadIdx.x);
+  const int t = threadIdx.x + 64 * threadIdx.y;
+  if (t < 64) {
+    ML.bs[t] = th[kOffB1 + t];
+    ML.bs[64 + t] = th[kOffB2 + t];
+    ML.bs[128 + t] = th[kOffW3 + t];
+  } else if (t == 64) {
+    ML.bs[192] = th[kOffB3];
+  }
+  __syncthreads();
+  const int kbeg = blockIdx.z * kchunk;
+  nodes_tile_block<R, kDt, true>(A, blockIdx.x, blockIdx.y, kbeg,
+                                 min(kbeg + kchunk, A.D.n[2]), Lp,
+                                 blockIdx.x + gridDim.x * (blockIdx.y + gridDim.y * blockIdx.z),
+                                 &ML);
 }
 
 // Persistent form over the members of a batch: item = (member, bx | by << 16,
@@ -979,6 +1062,17 @@ hipError_t launch_nodes(const StageArgs& A, hipStream_t s) {
   const int gx = (A.D.n[0] + 63) / 64, gy = (A.D.n[1] + 3) / 4;
   const int kchunk = nodes_kchunk(A.D);
   const dim3 grid(gx, gy, (A.D.n[2] + kchunk - 1) / kchunk), block(64, 4, 1);
+  if (A.mlp_fused) {
+    if (A.mixed && A.dtpart)
+      hipLaunchKernelGGL((k_nodes_tile_mlp<float, true>), grid, block, 0, s, A, kchunk);
+    else if (A.mixed)
+      hipLaunchKernelGGL(k_nodes_tile_mlp<float>, grid, block, 0, s, A, kchunk);
+    else if (A.dtpart)
+      hipLaunchKernelGGL((k_nodes_tile_mlp<double, true>), grid, block, 0, s, A, kchunk);
+    else
+      hipLaunchKernelGGL(k_nodes_tile_mlp<double>, grid, block, 0, s, A, kchunk);
+    return hipGetLastError();
+  }
   if (A.mixed && A.dtpart)
     hipLaunchKernelGGL((k_nodes_tile<float, true>), grid, block, 0, s, A, kchunk);
   else if (A.mixed)

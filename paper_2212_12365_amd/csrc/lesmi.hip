@@ -655,11 +655,19 @@ int run_stage(les_ctx* c, const double* q, int mode, double* out, const double* 
     A.dtpart = c->d_dtpart;
     A.flag = c->d_flag;
   }
+  if (c->params.closure == LES_MLP) {  // the closure evaluated inside the node kernel
+    A.mlp_fused = 1;
+    A.mlp.theta = c->mlp_theta;
+    A.mlp.norm = c->mlp_norm;
+    A.mlp.cs2 = (float)(c->params.cs * c->params.cs);
+    A.mlp_fallback = c->mlp_fallback;
+    A.feat = nullptr;
+    A.fscale = nullptr;
+  }
   const bool timed = mode == 1;
   int rc = timed ? prof_mark(c, s) : LES_OK;
   if (rc) return rc;
   hipError_t e = launch_nodes(A, s);
-  if (e == hipSuccess && c->params.closure == LES_MLP) e = run_mlp_closure(c, nullptr, s);
   if (e == hipSuccess && timed) rc = prof_mark(c, s);
   if (rc) return rc;
   if (e == hipSuccess && cfl > 0.0) {
