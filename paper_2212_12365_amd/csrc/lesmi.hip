@@ -7,6 +7,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <initializer_list>
 #include <new>
 #include <vector>
 
@@ -916,9 +917,18 @@ int les_dual_step(les_ctx* c, double* q, double* q_prev, int nsteps, double dt, 
   hipStream_t s = (hipStream_t)stream;
   const Dims& D = c->dims;
   const long long N = D.N;
-  if (!c->dual_qn && (dev_alloc(c, &c->dual_qn, 5 * N) || dev_alloc(c, &c->dual_qm, 5 * N) ||
-                      dev_alloc(c, &c->dual_rhs, 5 * N) || dev_alloc(c, &c->dual_dtau, N)))
-    return LES_ENOMEM;
+  if (!c->dual_qn || !c->dual_qm || !c->dual_rhs || !c->dual_dtau) {
+    double** bufs[4] = {&c->dual_qn, &c->dual_qm, &c->dual_rhs, &c->dual_dtau};
+    const long long counts[4] = {5 * N, 5 * N, 5 * N, N};
+    for (int b = 0; b < 4; ++b)
+      if (!*bufs[b] && dev_alloc(c, bufs[b], counts[b])) {
+        for (double** p : bufs) {  // all or none, so a later call starts afresh
+          if (*p) (void)hipFree(*p);
+          *p = nullptr;
+        }
+        return LES_ENOMEM;
+      }
+  }
   const long long nres = (long long)nsteps * subiters;
   if (nres > kMaxDualResiduals) return fail(c, LES_EINVAL, "nsteps x subiters too large");
   if (nres > c->dual_res_cap) {
@@ -1031,8 +1041,14 @@ int les_residual_norms(les_ctx* c, const double* q, double* out, void* stream) {
 int les_stats_reset(les_ctx* c) {
   if (!c) return LES_EINVAL;
   const long long N = c->dims.N;
-  if (!c->stat_sum && (dev_alloc(c, &c->stat_sum, 5 * N) || dev_alloc(c, &c->stat_sq, 5 * N)))
+  if ((!c->stat_sum && dev_alloc(c, &c->stat_sum, 5 * N)) ||
+      (!c->stat_sq && dev_alloc(c, &c->stat_sq, 5 * N))) {
+    for (double** p : {&c->stat_sum, &c->stat_sq}) {  // all or none
+      if (*p) (void)hipFree(*p);
+      *p = nullptr;
+    }
     return LES_ENOMEM;
+  }
   HIP_TRY(c, hipMemset(c->stat_sum, 0, 5 * N * sizeof(double)));
   HIP_TRY(c, hipMemset(c->stat_sq, 0, 5 * N * sizeof(double)));
   c->stat_n = 0;
@@ -1041,7 +1057,8 @@ int les_stats_reset(les_ctx* c) {
 
 int les_stats_accumulate(les_ctx* c, const double* q, void* stream) {
   if (!c || !q) return fail(c, LES_EINVAL, "null argument");
-  if (!c->stat_sum) return fail(c, LES_ESTATE, "statistics not started (les_stats_reset)");
+  if (!c->stat_sum || !c->stat_sq)
+    return fail(c, LES_ESTATE, "statistics not started (les_stats_reset)");
   hipLaunchKernelGGL(k_stats_acc, dim3(grid_for(c->dims.N)), dim3(kBlock), 0,
                      (hipStream_t)stream, c->dims, c->phys, q, c->stat_sum, c->stat_sq);
   int rc = launch_check(c, "statistics");
