@@ -63,26 +63,21 @@ __global__ void k_batch_gather(const MemberArgs* __restrict__ M, int n, double* 
   }
 }
 
-// Centreline means of the stage output; items (member, i).
-__global__ void __launch_bounds__(256) k_batch_axis(const StageArgs* __restrict__ row,
-                                                    const MemberArgs* __restrict__ M,
-                                                    const int4* __restrict__ work, int nwork) {
-  __shared__ double ring[5][kAxisChunk];
-  for (int w = blockIdx.x; w < nwork; w += gridDim.x) {
-    const int4 it = work[w];
-    const MemberArgs& m = M[it.x];
-    axis_mean_block(m.D, row[it.x].out, m.B.axis, it.y, ring);
-  }
-}
-
-// Boundary nodes of the stage output; items (member, block of 256 boundary nodes).
+// Boundary conditions of the stage output; items (member, i, 1): the centreline station i
+// (with the entrance and exit nodes on the axis); items (member, block, 0): 256 of the other
+// boundary nodes.
 __global__ void __launch_bounds__(256) k_batch_bc(const StageArgs* __restrict__ row,
                                                   const MemberArgs* __restrict__ M,
                                                   const int4* __restrict__ work, int nwork) {
+  __shared__ double ring[5][kAxisChunk];
+  __shared__ double mean[5];
   for (int w = blockIdx.x; w < nwork; w += gridDim.x) {
     const int4 it = work[w];
     const MemberArgs& m = M[it.x];
-    bc_node(m.D, m.P, m.B, row[it.x].out, (long long)it.y * 256 + threadIdx.x);
+    if (it.z)
+      bc_station_block(m.D, m.P, m.B, row[it.x].out, it.y, ring, mean);
+    else
+      bc_node(m.D, m.P, m.B, row[it.x].out, (long long)it.y * 256 + threadIdx.x);
   }
 }
 
@@ -124,9 +119,8 @@ struct les_batch {
   MemberArgs* d_mem = nullptr;  // [n]
   // Work lists: node kernel (tile, z-chunk), checks (64 x 4 block, plane), face kernel,
   // axis means, boundary nodes, time-step partials.
-  int4 *d_wnodes = nullptr, *d_wcheck = nullptr, *d_wfaces = nullptr, *d_waxis = nullptr,
-       *d_wbc = nullptr;
-  int nwnodes = 0, nwcheck = 0, nwfaces = 0, nwaxis = 0, nwbc = 0;
+  int4 *d_wnodes = nullptr, *d_wcheck = nullptr, *d_wfaces = nullptr, *d_wbc = nullptr;
+  int nwnodes = 0, nwcheck = 0, nwfaces = 0, nwbc = 0;
   double* d_dts = nullptr;
   int* d_flags = nullptr;
 
@@ -197,7 +191,7 @@ int build_face_work(les_batch* b) {
 }
 
 int build_static_work(les_batch* b) {
-  std::vector<int4> wn, wc, wa, wb;
+  std::vector<int4> wn, wc, wb;
   std::vector<MemberArgs> mem;
   for (int mi = 0; mi < (int)b->m.size(); ++mi) {
     les_ctx* c = b->m[mi];
@@ -213,10 +207,10 @@ int build_static_work(les_batch* b) {
         for (int bx = 0; bx < gx; ++bx)
           wn.push_back(make_int4(mi, bx | (by << 16), k0 | (std::min(k0 + kc, D.n[2]) << 16),
                                  slot++));
-    if (D.jet) {
-      for (int i = 1; i <= D.n[0] - 2; ++i) wa.push_back(make_int4(mi, i, 0, 0));
-      long long nbc = 2LL * (D.n[0] - 2) * D.n[2] + 2LL * D.n[1] * D.n[2];
-      for (long long blk = 0; blk * 256 < nbc; ++blk) wb.push_back(make_int4(mi, (int)blk, 0, 0));
+    if (D.jet) {  // the centreline stations first: they take longest
+      for (int i = 1; i <= D.n[0] - 2; ++i) wb.push_back(make_int4(mi, i, 1, 0));
+      for (long long blk = 0; blk * 256 < bc_count(D); ++blk)
+        wb.push_back(make_int4(mi, (int)blk, 0, 0));
     }
     MemberArgs M{};
     M.D = D;
@@ -233,11 +227,9 @@ int build_static_work(les_batch* b) {
   b->nwnodes = (int)wn.size();
   b->nwcheck = (int)wc.size();
   b->occ_nodes = occupancy_of(b, false);
-  b->nwaxis = (int)wa.size();
   b->nwbc = (int)wb.size();
   BHIP(b, upload(&b->d_wnodes, wn));
   BHIP(b, upload(&b->d_wcheck, wc));
-  BHIP(b, upload(&b->d_waxis, wa));
   BHIP(b, upload(&b->d_wbc, wb));
   BHIP(b, upload(&b->d_mem, mem));
   return LES_OK;
@@ -304,7 +296,7 @@ int enqueue_stage_kernels(les_batch* b, int row, hipStream_t s, double cfl = 0.0
 // One Runge-Kutta step of every member on stream s (no host synchronisation).
 int enqueue_step(les_batch* b, double cfl, double dt_fixed, hipStream_t s) {
   const int n = (int)b->m.size();
-  const int small = persistent_grid(b, 4, std::max(b->nwaxis, b->nwbc));
+  const int small = persistent_grid(b, 4, b->nwbc);
   if (!(cfl > 0.0))
     hipLaunchKernelGGL(k_batch_set_dt, dim3((n + 63) / 64), dim3(64), 0, s, b->d_mem, n, dt_fixed);
   int rc = check_launch(b, "batch time step");
@@ -312,10 +304,8 @@ int enqueue_step(les_batch* b, double cfl, double dt_fixed, hipStream_t s) {
   for (int l = 0; l < 5; ++l) {
     rc = enqueue_stage_kernels(b, l, s, l == 0 ? cfl : 0.0);
     if (rc) return rc;
-    if (b->nwaxis) {
+    if (b->nwbc) {
       const StageArgs* row = b->d_args + (size_t)l * n;
-      hipLaunchKernelGGL(k_batch_axis, dim3(small), dim3(256), 0, s, row, b->d_mem, b->d_waxis,
-                         b->nwaxis);
       hipLaunchKernelGGL(k_batch_bc, dim3(small), dim3(256), 0, s, row, b->d_mem, b->d_wbc,
                          b->nwbc);
       rc = check_launch(b, "batch boundary conditions");
@@ -526,7 +516,7 @@ void les_batch_destroy(les_batch* b) {
   drop_graph(b);
   if (b->cap) (void)hipStreamDestroy(b->cap);
   void* ptrs[] = {b->d_args, b->d_mem, b->d_wnodes, b->d_wcheck, b->d_wfaces,
-                  b->d_waxis, b->d_wbc, b->d_dts,    b->d_flags};
+                  b->d_wbc,   b->d_dts,  b->d_flags};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
   delete b;

@@ -33,13 +33,16 @@ __device__ void farfield_state(const Phys& P, const BcData& B, const double* qe,
   if (mn >= 1.0) {
     for (int c = 0; c < 5; ++c) qo[c] = qe[c];
     return;
-  } else if (mn >= 0.0) {
-    for (int c = 0; c < 3; ++c) uf[c] = ue[c] + (qnf - qne) * n[c];
-    rf = pow(pow(re, g) * af * af / (g * pe), P.inv_gm1);
-    pf = rf * af * af / g;
   } else if (mn > -1.0) {
-    for (int c = 0; c < 3; ++c) uf[c] = B.u_inf[c] + (qnf - qninf) * n[c];
-    rf = pow(pow(B.rho_inf, g) * af * af / (g * B.p_inf), P.inv_gm1);
+    // Subsonic: the entropy p / rho^gamma of the interior (outflow) or of the free stream
+    // (inflow) with the face sound speed af gives the density; along an isentrope
+    // rho_f = rho_ref (af / a_ref)^(2 / (gamma - 1)), one power instead of two.
+    const bool out = mn >= 0.0;
+    const double rr = out ? re : B.rho_inf, ar = out ? ae : ainf;
+    const double* ub = out ? ue : B.u_inf;
+    const double qb = out ? qne : qninf;
+    for (int c = 0; c < 3; ++c) uf[c] = ub[c] + (qnf - qb) * n[c];
+    rf = rr * pow(af / ar, 2.0 * P.inv_gm1);
     pf = rf * af * af / g;
   } else {
     for (int c = 0; c < 3; ++c) uf[c] = B.u_inf[c];
@@ -54,17 +57,20 @@ __device__ void farfield_state(const Phys& P, const BcData& B, const double* qe,
 }
 
 // Centreline means of the first ring, summed in k order (paper, Centerline Boundary
-// Condition). One block per axial station i: the ring is staged through LDS in chunks and
-// five threads add it up sequentially, so the sum order is k = 0, 1, ..., nk-1.
-constexpr int kAxisChunk = 1024;
+// Condition). One block per axial station i: the ring is staged through LDS in chunks of C
+// and five threads add it up sequentially, so the sum order is k = 0, 1, ..., nk-1 for any C.
+// The means go to axis[c * ni + i] and, with mean non-null, to mean[0..4] (LDS) for the
+// whole block.
+constexpr int kAxisChunk = 256;
+template <int C = kAxisChunk>
 __device__ __forceinline__ void axis_mean_block(const Dims& D, const double* __restrict__ q,
                                                 double* __restrict__ axis, int i,
-                                                double (&ring)[5][kAxisChunk]) {
+                                                double (&ring)[5][C], double* mean = nullptr) {
   const long long N = D.N;
   const int nk = D.n[2];
   double sum = 0.0;  // thread c < 5 accumulates component c
-  for (int kb = 0; kb < nk; kb += kAxisChunk) {
-    int len = min(kAxisChunk, nk - kb);
+  for (int kb = 0; kb < nk; kb += C) {
+    int len = min(C, nk - kb);
     for (int t = threadIdx.x; t < 5 * len; t += blockDim.x) {
       int c = t / len, k = kb + t % len;
       ring[c][k - kb] = q[(long long)c * N + nid(D, i, 1, k)];
@@ -74,101 +80,143 @@ __device__ __forceinline__ void axis_mean_block(const Dims& D, const double* __r
       for (int k = 0; k < len; ++k) sum += ring[threadIdx.x][k];
     __syncthreads();
   }
-  if (threadIdx.x < 5) axis[(long long)threadIdx.x * D.n[0] + i] = sum / (double)nk;
+  if (threadIdx.x < 5) {
+    const double m = sum / (double)nk;
+    axis[(long long)threadIdx.x * D.n[0] + i] = m;
+    if (mean) mean[threadIdx.x] = m;
+  }
+  if (mean) __syncthreads();
 }
 
 __device__ __forceinline__ void load_q(const double* q, long long N, long long id, double* o) {
   for (int c = 0; c < 5; ++c) o[c] = q[(long long)c * N + id];
 }
 
-// One thread per boundary node. Far field (j = nj-1, 1 <= i <= ni-2), centreline (j = 0,
-// 1 <= i <= ni-2), entrance (i = 0), exit (i = ni-1). Each boundary value is composed from
+// Entrance node (0, j, k), o = j + nj k: the jet state inside the jet, else the far-field
+// state from qe, the state of node (1, j, k) after the far field and centreline conditions.
+__device__ __forceinline__ void entrance_state(const Phys& P, const BcData& B, long long nface,
+                                               long long o, const double* qe, double* qo) {
+  if (B.jetmask[o]) {
+    const double uj = B.mach_jet;
+    qo[0] = 1.0;
+    qo[1] = uj;
+    qo[2] = 0.0;
+    qo[3] = 0.0;
+    qo[4] = (1.0 / P.gamma) * P.inv_gm1 + 0.5 * uj * uj;
+  } else {
+    const double n[3] = {B.nin[o], B.nin[nface + o], B.nin[2 * nface + o]};
+    farfield_state(P, B, qe, n, qo);
+  }
+}
+
+// Exit node (ni-1, j, k), o = j + nj k, from qe, the state of node (ni-2, j, k) after the far
+// field and centreline conditions: extrapolated where the normal Mach number is supersonic,
+// else p_inf with the interior's velocity and internal energy per unit mass.
+__device__ __forceinline__ void exit_state(const Phys& P, const BcData& B, long long nface,
+                                           long long o, const double* qe, double* qo) {
+  const double n[3] = {B.nex[o], B.nex[nface + o], B.nex[2 * nface + o]};
+  const double re = qe[0];
+  const double ue[3] = {qe[1] / re, qe[2] / re, qe[3] / re};
+  const double pe = P.gm1 * (qe[4] - 0.5 * re * (ue[0] * ue[0] + ue[1] * ue[1] + ue[2] * ue[2]));
+  const double ae = sqrt(P.gamma * pe / re);
+  const double mn = (ue[0] * n[0] + ue[1] * n[1] + ue[2] * n[2]) / ae;
+  if (mn >= 1.0) {
+    for (int c = 0; c < 5; ++c) qo[c] = qe[c];
+  } else {
+    const double eint = pe / (P.gm1 * re);
+    const double rb = B.p_inf / (P.gm1 * eint);
+    qo[0] = rb;
+    qo[1] = rb * ue[0];
+    qo[2] = rb * ue[1];
+    qo[3] = rb * ue[2];
+    qo[4] = B.p_inf * P.inv_gm1 + 0.5 * rb * (ue[0] * ue[0] + ue[1] * ue[1] + ue[2] * ue[2]);
+  }
+}
+
+// Boundary nodes other than the centreline's, one thread each: far field (j = nj-1,
+// 1 <= i <= ni-2), entrance (i = 0) and exit (i = ni-1), the last two without their j = 0
+// nodes, which take the centreline means (bc_station_block). Each value is composed from
 // updated nodes only, reproducing the order far field -> centreline -> entrance -> exit.
+__device__ __host__ __forceinline__ long long bc_count(const Dims& D) {
+  return (long long)(D.n[0] - 2) * D.n[2] + 2LL * D.n[1] * D.n[2];
+}
+
 __device__ __forceinline__ void bc_node(const Dims& D, const Phys& P, const BcData& B,
                                         double* __restrict__ q, long long t) {
-  int ni = D.n[0], nj = D.n[1], nk = D.n[2];
-  long long N = D.N;
-  long long nrow = (long long)(ni - 2) * nk;
-  long long nface = (long long)nj * nk;
-  double qe[5], qo[5], n[3];
-  auto ff_normal = [&](int i, int k, double* o) {
-    long long s = (long long)ni * nk, off = i + (long long)ni * k;
-    o[0] = B.nff[off];
-    o[1] = B.nff[s + off];
-    o[2] = B.nff[2 * s + off];
-  };
+  const int ni = D.n[0], nj = D.n[1];
+  const long long N = D.N;
+  const long long nrow = (long long)(ni - 2) * D.n[2];
+  const long long nface = (long long)nj * D.n[2];
+  double qe[5], qo[5];
   // Far-field state of node (i, nj-1, k), from its interior neighbour.
   auto farfield_node = [&](int i, int k, double* o) {
-    double qi[5], nn[3];
+    double qi[5];
     load_q(q, N, nid(D, i, nj - 2, k), qi);
-    ff_normal(i, k, nn);
+    const long long s = (long long)ni * D.n[2], off = i + (long long)ni * k;
+    const double nn[3] = {B.nff[off], B.nff[s + off], B.nff[2 * s + off]};
     farfield_state(P, B, qi, nn, o);
   };
-  // State of node (i, j, k) after the far field and centreline conditions.
+  // State of node (i, j, k), 1 <= j <= nj-1, after the far field condition.
   auto after_j = [&](int i, int j, int k, double* o) {
     if (j == nj - 1)
       farfield_node(i, k, o);
-    else if (j == 0)
-      for (int c = 0; c < 5; ++c) o[c] = B.axis[(long long)c * ni + i];
     else
       load_q(q, N, nid(D, i, j, k), o);
   };
   long long id;
   if (t < nrow) {  // far field
-    int i = 1 + (int)(t % (ni - 2)), k = (int)(t / (ni - 2));
+    const int i = 1 + (int)(t % (ni - 2)), k = (int)(t / (ni - 2));
     farfield_node(i, k, qo);
     id = nid(D, i, nj - 1, k);
-  } else if (t < 2 * nrow) {  // centreline
-    long long o = t - nrow;
-    int i = 1 + (int)(o % (ni - 2)), k = (int)(o / (ni - 2));
-    for (int c = 0; c < 5; ++c) qo[c] = B.axis[(long long)c * ni + i];
-    id = nid(D, i, 0, k);
-  } else if (t < 2 * nrow + nface) {  // entrance
-    long long o = t - 2 * nrow;
-    int j = (int)(o % nj), k = (int)(o / nj);
+  } else if (t < nrow + nface) {  // entrance
+    const long long o = t - nrow;
+    const int j = (int)(o % nj), k = (int)(o / nj);
+    if (j == 0) return;
     id = nid(D, 0, j, k);
-    if (B.jetmask[o]) {
-      double uj = B.mach_jet;
-      qo[0] = 1.0;
-      qo[1] = uj;
-      qo[2] = 0.0;
-      qo[3] = 0.0;
-      qo[4] = (1.0 / P.gamma) * P.inv_gm1 + 0.5 * uj * uj;
-    } else {
-      after_j(1, j, k, qe);
-      n[0] = B.nin[o];
-      n[1] = B.nin[nface + o];
-      n[2] = B.nin[2 * nface + o];
-      farfield_state(P, B, qe, n, qo);
-    }
-  } else if (t < 2 * nrow + 2 * nface) {  // exit
-    long long o = t - 2 * nrow - nface;
-    int j = (int)(o % nj), k = (int)(o / nj);
+    if (!B.jetmask[o]) after_j(1, j, k, qe);
+    entrance_state(P, B, nface, o, qe, qo);
+  } else if (t < nrow + 2 * nface) {  // exit
+    const long long o = t - nrow - nface;
+    const int j = (int)(o % nj), k = (int)(o / nj);
+    if (j == 0) return;
     id = nid(D, ni - 1, j, k);
     after_j(ni - 2, j, k, qe);
-    n[0] = B.nex[o];
-    n[1] = B.nex[nface + o];
-    n[2] = B.nex[2 * nface + o];
-    double re = qe[0];
-    double ue[3] = {qe[1] / re, qe[2] / re, qe[3] / re};
-    double pe = P.gm1 * (qe[4] - 0.5 * re * (ue[0] * ue[0] + ue[1] * ue[1] + ue[2] * ue[2]));
-    double ae = sqrt(P.gamma * pe / re);
-    double mn = (ue[0] * n[0] + ue[1] * n[1] + ue[2] * n[2]) / ae;
-    if (mn >= 1.0) {
-      for (int c = 0; c < 5; ++c) qo[c] = qe[c];
-    } else {
-      double eint = pe / (P.gm1 * re);
-      double rb = B.p_inf / (P.gm1 * eint);
-      qo[0] = rb;
-      qo[1] = rb * ue[0];
-      qo[2] = rb * ue[1];
-      qo[3] = rb * ue[2];
-      qo[4] = B.p_inf * P.inv_gm1 + 0.5 * rb * (ue[0] * ue[0] + ue[1] * ue[1] + ue[2] * ue[2]);
-    }
+    exit_state(P, B, nface, o, qe, qo);
   } else {
     return;
   }
   for (int c = 0; c < 5; ++c) q[(long long)c * N + id] = qo[c];
+}
+
+// Centreline nodes of axial station i, 1 <= i <= ni-2 (one block): the means of ring j = 1
+// (also left in B.axis), written to nodes (i, 0, k); station 1's block also writes the
+// entrance nodes (0, 0, k) and station ni-2's the exit nodes (ni-1, 0, k), whose interior
+// neighbours are those centreline nodes.
+template <int C>
+__device__ __forceinline__ void bc_station_block(const Dims& D, const Phys& P, const BcData& B,
+                                                 double* __restrict__ q, int i,
+                                                 double (&ring)[5][C], double* mean) {
+  axis_mean_block<C>(D, q, B.axis, i, ring, mean);
+  const int ni = D.n[0], nj = D.n[1], nk = D.n[2];
+  const long long N = D.N, nface = (long long)nj * nk;
+  double m[5];
+  for (int c = 0; c < 5; ++c) m[c] = mean[c];
+  for (int k = threadIdx.x; k < nk; k += blockDim.x) {
+    const long long id = nid(D, i, 0, k);
+    for (int c = 0; c < 5; ++c) q[(long long)c * N + id] = m[c];
+    double qo[5];
+    const long long o = (long long)nj * k;
+    if (i == 1) {
+      entrance_state(P, B, nface, o, m, qo);
+      const long long e = nid(D, 0, 0, k);
+      for (int c = 0; c < 5; ++c) q[(long long)c * N + e] = qo[c];
+    }
+    if (i == ni - 2) {
+      exit_state(P, B, nface, o, m, qo);
+      const long long e = nid(D, ni - 1, 0, k);
+      for (int c = 0; c < 5; ++c) q[(long long)c * N + e] = qo[c];
+    }
+  }
 }
 
 // ---------------------------------------------------------------------------------------

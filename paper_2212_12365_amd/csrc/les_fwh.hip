@@ -17,7 +17,7 @@
 //  * les_fwh_pressure: the sources Q_n, L_i of every sample and their time derivatives
 //    (central differences, second-order one-sided at both ends), then one block per
 //    observer and group of observer times: the block's threads take the surface nodes in a
-//    fixed strided order, interpolate the sources linearly at each node's retarded time, and
+//    fixed strided order, interpolate each node's term linearly at its retarded time, and
 //    the block sums the terms of each time in a fixed tree order, so the result does not
 //    depend on scheduling.
 #include <hip/hip_runtime.h>
@@ -158,10 +158,13 @@ constexpr int kFwhTimes = 8;
 
 // One block per (observer a, group of kFwhTimes consecutive observer times): p'[a][b], the
 // sum of the absolute terms (scale) and the number of nodes whose retarded time lies outside
-// the samples, for each time b of the group. A node's distance, unit vector and the factors
-// 1/r, 1/(c0 r), 1/r^2 do not depend on the time, so each thread forms them once per node
-// and then takes the group's times; for every (a, b) the nodes are summed in the same
-// strided order and the same tree as with one block per (a, b).
+// the samples, for each time b of the group. A node's term is linear in its seven sources,
+// g_m = dS (dQ_n/dtau / r + dL_r/dtau / (c0 r) + L_r / r^2) at sample m, and the linear
+// interpolation at the retarded time commutes with that combination, so each thread forms
+// the node's seven coefficients once and then g_m of the samples the group's retarded times
+// fall between, keeping the last pair: for times a fraction of a sample apart, consecutive
+// times reuse one or both values instead of gathering 14 sources each. For every (a, b) the
+// nodes are summed in the same strided order and the same tree as with one block per (a, b).
 __global__ void __launch_bounds__(kFwhBlock)
     k_fwh_integrate(int ns, int M, double tau0, double dtau, double c0,
                     const double* __restrict__ geo, const double* __restrict__ src,
@@ -179,19 +182,35 @@ __global__ void __launch_bounds__(kFwhBlock)
   const int a = item % no, b0 = (item / no) * kFwhTimes;
   const int nb = nt - b0 < kFwhTimes ? nt - b0 : kFwhTimes;
   const double x = obs[3 * a], y = obs[3 * a + 1], z = obs[3 * a + 2];
-  double tb[kFwhTimes], sum[kFwhTimes], abs_sum[kFwhTimes], skip[kFwhTimes];
+  double tb[kFwhTimes], sum[kFwhTimes], abs_sum[kFwhTimes];
+  int skip[kFwhTimes];
 #pragma unroll
   for (int u = 0; u < kFwhTimes; ++u) {
     tb[u] = u < nb ? times[b0 + u] : 0.0;
-    sum[u] = abs_sum[u] = skip[u] = 0.0;
+    sum[u] = abs_sum[u] = 0.0;
+    skip[u] = 0;
   }
   for (int s = threadIdx.x; s < ns; s += kFwhBlock) {
     const double dx = x - geo[s], dy = y - geo[ns + s], dz = z - geo[2 * ns + s];
     const double r = sqrt(dx * dx + dy * dy + dz * dz);
     const double rh0 = dx / r, rh1 = dy / r, rh2 = dz / r;
     const double rc = r / c0;
-    const double ir = 1.0 / r, icr = 1.0 / (c0 * r), ir2 = 1.0 / (r * r);
     const double area = geo[6 * ns + s];
+    // g_m = cq dQ_n/dtau + cl . L + cd . dL/dtau
+    const double cq = area / r, cr2 = area / (r * r), ccr = area / (c0 * r);
+    const double cl[3] = {cr2 * rh0, cr2 * rh1, cr2 * rh2};
+    const double cd[3] = {ccr * rh0, ccr * rh1, ccr * rh2};
+    auto g_at = [&](int m) {
+      const double* sm = src + (size_t)m * 7 * ns + s;
+      double g = cq * sm[0];
+#pragma unroll
+      for (int c = 0; c < 3; ++c) g = fma(cl[c], sm[(1 + c) * ns], g);
+#pragma unroll
+      for (int c = 0; c < 3; ++c) g = fma(cd[c], sm[(4 + c) * ns], g);
+      return g;
+    };
+    int cm = -2;  // g_lo = g_cm, g_hi = g_{cm+1}
+    double g_lo = 0.0, g_hi = 0.0;
 #pragma unroll
     for (int u = 0; u < kFwhTimes; ++u) {
       if (u >= nb) break;
@@ -203,17 +222,17 @@ __global__ void __launch_bounds__(kFwhBlock)
         ok = true;
       }
       if (!ok) {
-        skip[u] += 1.0;
+        skip[u] += 1;
         continue;
       }
+      if (m != cm) {
+        const double lo = m == cm + 1 ? g_hi : g_at(m);
+        g_hi = g_at(m + 1);
+        g_lo = lo;
+        cm = m;
+      }
       const double w = sm - m;
-      const double* s0 = src + (size_t)m * 7 * ns;
-      const double* s1 = s0 + 7 * ns;
-      auto at = [&](int c) { return (1.0 - w) * s0[c * ns + s] + w * s1[c * ns + s]; };
-      const double qd = at(0);
-      const double lr = at(1) * rh0 + at(2) * rh1 + at(3) * rh2;
-      const double ldr = at(4) * rh0 + at(5) * rh1 + at(6) * rh2;
-      const double term = area * (qd * ir + ldr * icr + lr * ir2);
+      const double term = (1.0 - w) * g_lo + w * g_hi;
       sum[u] += term;
       abs_sum[u] += fabs(term);
     }
@@ -222,7 +241,7 @@ __global__ void __launch_bounds__(kFwhBlock)
   for (int u = 0; u < nb; ++u) {
     red[0][threadIdx.x] = sum[u];
     red[1][threadIdx.x] = abs_sum[u];
-    red[2][threadIdx.x] = skip[u];
+    red[2][threadIdx.x] = (double)skip[u];
     __syncthreads();
     for (int h = kFwhBlock / 2; h > 0; h >>= 1) {
       if ((int)threadIdx.x < h)

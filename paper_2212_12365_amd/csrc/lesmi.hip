@@ -179,14 +179,17 @@ __global__ void k_bc_normals(Dims D, const double* __restrict__ S, BcData B) {
 // ---------------------------------------------------------------------------------------
 // Boundary conditions, time step and state check (bodies in les_bcdt.h).
 // ---------------------------------------------------------------------------------------
-__global__ void __launch_bounds__(256) k_axis_mean(Dims D, const double* __restrict__ q,
-                                                   double* __restrict__ axis) {
+// All boundary conditions of a state in one launch: blocks 0 .. ni-3 are the centreline
+// stations i = 1 .. ni-2 (with the entrance and exit nodes on the axis), the rest take 256
+// of the other boundary nodes each.
+__global__ void __launch_bounds__(256) k_bc(Dims D, Phys P, BcData B, double* __restrict__ q) {
   __shared__ double ring[5][kAxisChunk];
-  axis_mean_block(D, q, axis, blockIdx.x + 1, ring);
-}
-
-__global__ void k_bc(Dims D, Phys P, BcData B, double* __restrict__ q) {
-  bc_node(D, P, B, q, (long long)blockIdx.x * blockDim.x + threadIdx.x);
+  __shared__ double mean[5];
+  const int ns = D.n[0] - 2;
+  if ((int)blockIdx.x < ns)
+    bc_station_block(D, P, B, q, (int)blockIdx.x + 1, ring, mean);
+  else
+    bc_node(D, P, B, q, (long long)(blockIdx.x - ns) * 256 + threadIdx.x);
 }
 
 __global__ void __launch_bounds__(256) k_dt_final(const double* __restrict__ part, int nparts,
@@ -689,9 +692,8 @@ int run_stage(les_ctx* c, const double* q, int mode, double* out, const double* 
 int run_bc(les_ctx* c, double* q, hipStream_t s) {
   const Dims& D = c->dims;
   if (!D.jet) return LES_OK;
-  hipLaunchKernelGGL(k_axis_mean, dim3(D.n[0] - 2), dim3(kBlock), 0, s, D, q, c->bc.axis);
-  long long nbc = 2LL * (D.n[0] - 2) * D.n[2] + 2LL * D.n[1] * D.n[2];
-  hipLaunchKernelGGL(k_bc, dim3(grid_for(nbc)), dim3(kBlock), 0, s, D, c->phys, c->bc, q);
+  hipLaunchKernelGGL(k_bc, dim3((D.n[0] - 2) + grid_for(bc_count(D), 256)), dim3(256), 0, s, D,
+                     c->phys, c->bc, q);
   return launch_check(c, "boundary kernels");
 }
 
