@@ -190,16 +190,18 @@ __global__ void __launch_bounds__(kFwhBlock)
     sum[u] = abs_sum[u] = 0.0;
     skip[u] = 0;
   }
+  const double ic0 = 1.0 / c0;
   for (int s = threadIdx.x; s < ns; s += kFwhBlock) {
     const double dx = x - geo[s], dy = y - geo[ns + s], dz = z - geo[2 * ns + s];
     const double r = sqrt(dx * dx + dy * dy + dz * dz);
-    const double rh0 = dx / r, rh1 = dy / r, rh2 = dz / r;
-    const double rc = r / c0;
+    const double ir = 1.0 / r;
+    const double rc = r / c0;  // the retarded time is formed as the oracle forms it
     const double area = geo[6 * ns + s];
     // g_m = cq dQ_n/dtau + cl . L + cd . dL/dtau
-    const double cq = area / r, cr2 = area / (r * r), ccr = area / (c0 * r);
-    const double cl[3] = {cr2 * rh0, cr2 * rh1, cr2 * rh2};
-    const double cd[3] = {ccr * rh0, ccr * rh1, ccr * rh2};
+    const double cq = area * ir, cr2 = cq * ir, ccr = cq * ic0;
+    const double rh[3] = {dx * ir, dy * ir, dz * ir};
+    const double cl[3] = {cr2 * rh[0], cr2 * rh[1], cr2 * rh[2]};
+    const double cd[3] = {ccr * rh[0], ccr * rh[1], ccr * rh[2]};
     auto g_at = [&](int m) {
       const double* sm = src + (size_t)m * 7 * ns + s;
       double g = cq * sm[0];
@@ -209,32 +211,72 @@ __global__ void __launch_bounds__(kFwhBlock)
       for (int c = 0; c < 3; ++c) g = fma(cd[c], sm[(4 + c) * ns], g);
       return g;
     };
-    int cm = -2;  // g_lo = g_cm, g_hi = g_{cm+1}
-    double g_lo = 0.0, g_hi = 0.0;
+    // Interval m_u and weight of each time of the group (the same division and floor as
+    // one time at a time, so the interval decisions do not depend on the grouping).
+    double wt[kFwhTimes];
+    int mu[kFwhTimes];
+    bool ok[kFwhTimes];
 #pragma unroll
     for (int u = 0; u < kFwhTimes; ++u) {
-      if (u >= nb) break;
       const double sm = (tb[u] - rc - tau0) / dtau;
       int m = (int)floor(sm);
-      bool ok = m >= 0 && m + 1 <= M - 1;
-      if (m == M - 1 && sm == (double)(M - 1)) {  // exactly on the last sample
+      bool in = u < nb && m >= 0 && m + 1 <= M - 1;
+      if (u < nb && m == M - 1 && sm == (double)(M - 1)) {  // exactly on the last sample
         m = M - 2;
-        ok = true;
+        in = true;
       }
-      if (!ok) {
-        skip[u] += 1;
-        continue;
+      ok[u] = in;
+      mu[u] = in ? m : 0;
+      wt[u] = in ? sm - m : 0.0;
+    }
+    // Regular node: every retarded time inside the samples from the first on, each at most
+    // one interval past the previous one (times less than a sample apart, in order). Then
+    // g at m_0 and at m_u + 1 for every u are all the values needed, and their loads do not
+    // wait on one another.
+    bool regular = true;
+#pragma unroll
+    for (int u = 1; u < kFwhTimes; ++u) {
+      const int d = mu[u] - mu[u - 1];
+      if (ok[u] && (!ok[u - 1] || d < 0 || d > 1)) regular = false;
+    }
+    if (regular) {
+      double gn[kFwhTimes];
+      const double g0 = g_at(mu[0]);
+#pragma unroll
+      for (int u = 0; u < kFwhTimes; ++u) gn[u] = g_at(mu[u] + 1);
+      double g_lo = g0;
+#pragma unroll
+      for (int u = 0; u < kFwhTimes; ++u) {
+        if (u > 0 && mu[u] == mu[u - 1] + 1) g_lo = gn[u - 1];
+        const double term = (1.0 - wt[u]) * g_lo + wt[u] * gn[u];
+        if (ok[u]) {
+          sum[u] += term;
+          abs_sum[u] += fabs(term);
+        } else if (u < nb) {
+          skip[u] += 1;
+        }
       }
-      if (m != cm) {
-        const double lo = m == cm + 1 ? g_hi : g_at(m);
-        g_hi = g_at(m + 1);
-        g_lo = lo;
-        cm = m;
+    } else {  // times out of order, far apart or partly outside: the last pair is kept
+      int cm = -2;  // g_lo = g_cm, g_hi = g_{cm+1}
+      double g_lo = 0.0, g_hi = 0.0;
+#pragma unroll
+      for (int u = 0; u < kFwhTimes; ++u) {
+        if (u >= nb) break;
+        if (!ok[u]) {
+          skip[u] += 1;
+          continue;
+        }
+        const int m = mu[u];
+        if (m != cm) {
+          const double lo = m == cm + 1 ? g_hi : g_at(m);
+          g_hi = g_at(m + 1);
+          g_lo = lo;
+          cm = m;
+        }
+        const double term = (1.0 - wt[u]) * g_lo + wt[u] * g_hi;
+        sum[u] += term;
+        abs_sum[u] += fabs(term);
       }
-      const double w = sm - m;
-      const double term = (1.0 - w) * g_lo + w * g_hi;
-      sum[u] += term;
-      abs_sum[u] += fabs(term);
     }
   }
   const double k = 1.0 / (4.0 * M_PI);
