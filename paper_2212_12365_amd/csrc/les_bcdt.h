@@ -57,8 +57,9 @@ __device__ void farfield_state(const Phys& P, const BcData& B, const double* qe,
 }
 
 // Centreline means of the first ring, summed in k order (paper, Centerline Boundary
-// Condition). One block per axial station i: the ring is staged through LDS in chunks of C
-// and five threads add it up sequentially, so the sum order is k = 0, 1, ..., nk-1 for any C.
+// Condition). One 256-thread block per axial station i: the ring is staged through LDS in
+// chunks of C and five threads add it up sequentially, so the sum order is k = 0, 1, ...,
+// nk-1 for any C.
 // The means go to axis[c * ni + i] and, with mean non-null, to mean[0..4] (LDS) for the
 // whole block.
 constexpr int kAxisChunk = 256;
@@ -69,11 +70,19 @@ __device__ __forceinline__ void axis_mean_block(const Dims& D, const double* __r
   const long long N = D.N;
   const int nk = D.n[2];
   double sum = 0.0;  // thread c < 5 accumulates component c
+  constexpr int kPer = (5 * C + 255) / 256;  // ring values per thread of a 256-thread block
   for (int kb = 0; kb < nk; kb += C) {
-    int len = min(C, nk - kb);
-    for (int t = threadIdx.x; t < 5 * len; t += blockDim.x) {
-      int c = t / len, k = kb + t % len;
-      ring[c][k - kb] = q[(long long)c * N + nid(D, i, 1, k)];
+    const int len = min(C, nk - kb);
+    double v[kPer];  // all of the thread's loads are issued before the first LDS store
+#pragma unroll
+    for (int r = 0; r < kPer; ++r) {
+      const int t = threadIdx.x + 256 * r;
+      if (t < 5 * len) v[r] = q[(long long)(t / len) * N + nid(D, i, 1, kb + t % len)];
+    }
+#pragma unroll
+    for (int r = 0; r < kPer; ++r) {
+      const int t = threadIdx.x + 256 * r;
+      if (t < 5 * len) ring[t / len][t % len] = v[r];
     }
     __syncthreads();
     if (threadIdx.x < 5)
