@@ -38,10 +38,11 @@ def case(name):
         return p, xyz, smooth_field(xyz, p.gamma, seed=7)
     if name.startswith("jet"):
         # jet_mesh6 and jet_mesh10: meshes 6 and 10 of the paper's mesh table (a thin
-        # azimuthal direction, and the table's smallest mesh).
+        # azimuthal direction, and the table's smallest mesh); jet_wide: more azimuthal nodes
+        # than one LDS chunk of the centreline mean (256) and the fewest axial stations.
         shapes = {"jet_small": (64, 48, 32), "jet_ragged": (37, 21, 12),
                   "jet_c2": (256, 128, 128), "jet_mesh6": (400, 150, 10),
-                  "jet_mesh10": (200, 75, 20)}
+                  "jet_mesh10": (200, 75, 20), "jet_wide": (5, 9, 300)}
         n = shapes[name]
         xyz, _ = jet_grid(n)
         p = sy.jet_params(n)

@@ -87,7 +87,7 @@ def test_sgs_viscosity(torch, name):
     ctx.close()
 
 
-@pytest.mark.parametrize("name", ["jet_ragged", "jet_small"])
+@pytest.mark.parametrize("name", ["jet_ragged", "jet_small", "jet_wide"])
 def test_apply_bc(torch, name):
     _announce(f"bc {name}")
     p, xyz, q = case(name)
@@ -107,7 +107,7 @@ def test_apply_bc(torch, name):
 
 @pytest.mark.parametrize("name,nsteps", [("tgv32", 20), ("skew24", 5), ("jet_small", 5),
                                          ("jet_ragged", 8), ("skew_odd", 6),
-                                         ("jet_mesh10", 3)])
+                                         ("jet_mesh10", 3), ("jet_wide", 3)])
 def test_step(torch, name, nsteps):
     _announce(f"step {name} x{nsteps}")
     p, xyz, q = case(name)
