@@ -45,6 +45,11 @@ struct StageArgs {
   // and a non-positive density or pressure or a non-finite ratio sets bit 2 of *flag.
   double* dtpart;
   int* flag;
+  // Local pseudo-time steps of dual time stepping (null: off): the node kernel writes
+  // dtau_out[o] = cfl_tau J^-1 / (sum of the three spectral radii) in FP64 at updated nodes
+  // and 0 elsewhere.
+  double* dtau_out;
+  double cfl_tau;
   int tile;   // k_stage_planes tile shape, index into kTileNames
   int kmin;   // smallest z-chunk depth (0 = default)
   // Learned closure (k_nodes): inputs [6][N], scale rho Delta^2 |S| [N] and |S| [N] of the

@@ -100,7 +100,7 @@ constexpr int kNodeTileX = 66, kNodeTileY = 6, kNodeTileN = kNodeTileX * kNodeTi
 // With mlp_in non-null the eddy-viscosity record is left to the caller and the closure's
 // inputs come back in mlp_in[0..5], its scale rho Delta^2 |S| in mlp_in[6] (as FP32, the
 // values the inference kernel would read).
-template <typename R, bool kQueue>
+template <typename R, bool kQueue, bool kTau = false>
 __device__ __forceinline__ void node_record(const StageArgs& A, int i, int j, int k,
                                             const Prim& zm, const Prim& z0, const Prim& zp,
                                             const R* nl = nullptr, int npos = 0,
@@ -168,20 +168,27 @@ __device__ __forceinline__ void node_record(const StageArgs& A, int i, int j, in
   const R l0 = spectral<R>(sm[0], sm[1], sm[2], su, sv, sw, a);
   const R l1 = spectral<R>(sm[3], sm[4], sm[5], su, sv, sw, a);
   const R l2 = spectral<R>(sm[6], sm[7], sm[8], su, sv, sw, a);
-  if (rdt && is_updated(D, i, j, k)) {  // the node's term of the time-step reduction
+  const bool upd = is_updated(D, i, j, k);
+  if ((rdt && upd) || kTau) {
+    // The node's term of the time-step reduction, or its local pseudo-time step: the sum of
+    // the spectral radii in FP64 (from the FP64 metrics in the mixed form), the same
+    // operations on the same values as the separate FP64 passes.
     double l;
     if constexpr (sizeof(R) == sizeof(double)) {
       l = l0 + l1 + l2;
-    } else {  // in FP64 from the FP64 metrics, as the separate reduction takes it
+    } else {
       const double* __restrict__ S64 = A.S;
       const double a64 = sqrt(s.T);
       l = spectral(S64[o], S64[N + o], S64[2 * N + o], s.u, s.v, s.w, a64) +
           spectral(S64[3 * N + o], S64[4 * N + o], S64[5 * N + o], s.u, s.v, s.w, a64) +
           spectral(S64[6 * N + o], S64[7 * N + o], S64[8 * N + o], s.u, s.v, s.w, a64);
     }
-    const double r = A.jinv[o] / l;
-    if (!(s.rho > 0.0) || !(s.p > 0.0) || !isfinite(r)) atomicOr(A.flag, 2);
-    *rdt = fmin(*rdt, r);
+    if (rdt && upd) {
+      const double r = A.jinv[o] / l;
+      if (!(s.rho > 0.0) || !(s.p > 0.0) || !isfinite(r)) atomicOr(A.flag, 2);
+      *rdt = fmin(*rdt, r);
+    }
+    if (kTau) A.dtau_out[o] = upd ? A.cfl_tau * A.jinv[o] / l : 0.0;
   }
   R lb[3];
   scaled_radii<R>(l0, l1, l2, lb);
@@ -237,7 +244,7 @@ struct NodeMlpLds {
   __bf16 Hl[4][16 * HS];
 };
 
-template <typename R, bool kDt = false, bool kMlp = false>
+template <typename R, bool kDt = false, bool kMlp = false, bool kTau = false>
 __device__ __forceinline__ void nodes_tile_block(const StageArgs& A, int bx, int by, int kbeg,
                                                  int kend, R* Lp, int slot = 0,
                                                  NodeMlpLds* ML = nullptr) {
@@ -315,7 +322,8 @@ __device__ __forceinline__ void nodes_tile_block(const StageArgs& A, int bx, int
 #pragma unroll
       for (int c = 0; c <= kMlpIn; ++c) fin[c] = 0.f;
       if (mine)
-        node_record<R, true>(A, il, jl, k, zm, z0, zp, Lp, ol, kDt ? &rdt : nullptr, fin);
+        node_record<R, true, kTau>(A, il, jl, k, zm, z0, zp, Lp, ol, kDt ? &rdt : nullptr,
+                                   fin);
       float x[kMlpIn];
       const bool ok = mlp_input(A.mlp, fin, fin[kMlpIn], x);
       const int lane = tx, g = lane >> 4, sl = lane & 15;
@@ -335,7 +343,8 @@ __device__ __forceinline__ void nodes_tile_block(const StageArgs& A, int bx, int
         records_of<R>(A)[kRecMut * N + (il + ni * (jl + nj * k))] = (R)mu;
       }
     } else {
-      if (mine) node_record<R, true>(A, il, jl, k, zm, z0, zp, Lp, ol, kDt ? &rdt : nullptr);
+      if (mine)
+        node_record<R, true, kTau>(A, il, jl, k, zm, z0, zp, Lp, ol, kDt ? &rdt : nullptr);
     }
     zm = z0;
     z0 = zp;
@@ -356,18 +365,20 @@ __device__ __forceinline__ void nodes_tile_block(const StageArgs& A, int bx, int
   }
 }
 
-// kDt: also the time-step reduction's block minima (A.dtpart).
-template <typename R, bool kDt = false>
+// kDt: also the time-step reduction's block minima (A.dtpart); kTau: also the local
+// pseudo-time steps (A.dtau_out).
+template <typename R, bool kDt = false, bool kTau = false>
 __global__ void __launch_bounds__(256) k_nodes_tile(StageArgs A, int kchunk) {
   __shared__ R Lp[4 * kNodeTileN];
   const int kbeg = blockIdx.z * kchunk;
-  nodes_tile_block<R, kDt>(A, blockIdx.x, blockIdx.y, kbeg, min(kbeg + kchunk, A.D.n[2]), Lp,
-                           blockIdx.x + gridDim.x * (blockIdx.y + gridDim.y * blockIdx.z));
+  nodes_tile_block<R, kDt, false, kTau>(
+      A, blockIdx.x, blockIdx.y, kbeg, min(kbeg + kchunk, A.D.n[2]), Lp,
+      blockIdx.x + gridDim.x * (blockIdx.y + gridDim.y * blockIdx.z));
 }
 
 // The same with the learned closure evaluated for each plane's nodes (StageArgs.mlp_fused):
 // the block first lays the network's weight fragments into LDS.
-template <typename R, bool kDt = false>
+template <typename R, bool kDt = false, bool kTau = false>
 __global__ void __launch_bounds__(256) k_nodes_tile_mlp(StageArgs A, int kchunk) {
   __shared__ R Lp[4 * kNodeTileN];
   __shared__ NodeMlpLds ML;
@@ -383,10 +394,9 @@ __global__ void __launch_bounds__(256) k_nodes_tile_mlp(StageArgs A, int kchunk)
   }
   __syncthreads();
   const int kbeg = blockIdx.z * kchunk;
-  nodes_tile_block<R, kDt, true>(A, blockIdx.x, blockIdx.y, kbeg,
-                                 min(kbeg + kchunk, A.D.n[2]), Lp,
-                                 blockIdx.x + gridDim.x * (blockIdx.y + gridDim.y * blockIdx.z),
-                                 &ML);
+  nodes_tile_block<R, kDt, true, kTau>(
+      A, blockIdx.x, blockIdx.y, kbeg, min(kbeg + kchunk, A.D.n[2]), Lp,
+      blockIdx.x + gridDim.x * (blockIdx.y + gridDim.y * blockIdx.z), &ML);
 }
 
 // Persistent form over the members of a batch: item = (member, bx | by << 16,
@@ -1062,6 +1072,18 @@ hipError_t launch_nodes(const StageArgs& A, hipStream_t s) {
   const int gx = (A.D.n[0] + 63) / 64, gy = (A.D.n[1] + 3) / 4;
   const int kchunk = nodes_kchunk(A.D);
   const dim3 grid(gx, gy, (A.D.n[2] + kchunk - 1) / kchunk), block(64, 4, 1);
+  if (A.dtau_out) {  // dual time stepping: no time-step reduction beside it
+    if (A.dtpart) return hipErrorInvalidValue;
+    if (A.mlp_fused && A.mixed)
+      hipLaunchKernelGGL((k_nodes_tile_mlp<float, false, true>), grid, block, 0, s, A, kchunk);
+    else if (A.mlp_fused)
+      hipLaunchKernelGGL((k_nodes_tile_mlp<double, false, true>), grid, block, 0, s, A, kchunk);
+    else if (A.mixed)
+      hipLaunchKernelGGL((k_nodes_tile<float, false, true>), grid, block, 0, s, A, kchunk);
+    else
+      hipLaunchKernelGGL((k_nodes_tile<double, false, true>), grid, block, 0, s, A, kchunk);
+    return hipGetLastError();
+  }
   if (A.mlp_fused) {
     if (A.mixed && A.dtpart)
       hipLaunchKernelGGL((k_nodes_tile_mlp<float, true>), grid, block, 0, s, A, kchunk);

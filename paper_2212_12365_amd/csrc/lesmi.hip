@@ -381,29 +381,9 @@ __global__ void __launch_bounds__(256) k_rhs_norm_final(const double* __restrict
 // point-implicit in each stage.
 // ---------------------------------------------------------------------------------------
 
-// Local pseudo-time step cfl_tau J^-1 / sum_d (|S_d . u| + a |S_d|) at updated nodes, 0
-// elsewhere, from the state q.
-__global__ void k_local_dtau(Dims D, Phys P, const double* __restrict__ q,
-                             const double* __restrict__ S, const double* __restrict__ jinv,
-                             double cfl_tau, double* __restrict__ dtau) {
-  const long long o = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (o >= D.N) return;
-  const long long N = D.N;
-  const int i = (int)(o % D.n[0]), j = (int)((o / D.n[0]) % D.n[1]),
-            k = (int)(o / ((long long)D.n[0] * D.n[1]));
-  if (!is_updated(D, i, j, k)) {
-    dtau[o] = 0.0;
-    return;
-  }
-  const Prim s = prim_from_q(q[o], q[N + o], q[2 * N + o], q[3 * N + o], q[4 * N + o], P);
-  const double a = sqrt(s.T);
-  double lam = 0.0;
-  for (int d = 0; d < 3; ++d)
-    lam += spectral(S[(3 * d) * N + o], S[(3 * d + 1) * N + o], S[(3 * d + 2) * N + o], s.u, s.v,
-                    s.w, a);
-  dtau[o] = cfl_tau * jinv[o] / lam;
-}
-
+// The local pseudo-time step cfl_tau J^-1 / sum_d (|S_d . u| + a |S_d|) at updated nodes (0
+// elsewhere) of an iteration's starting state is written by the node kernel of the
+// iteration's first stage (StageArgs.dtau_out).
 struct DualArgs {
   Dims D;
   const double* q0;    // state at the start of the pseudo-time iteration
@@ -647,8 +627,11 @@ int prof_mark(les_ctx* c, hipStream_t s) {
 // residual (mode 0) or the Runge-Kutta stage update (mode 1) as the epilogue.
 // With cfl > 0, the node kernel also reduces the time step of this stage's input (its block
 // minima, then k_dt_final) before the face kernel uses it.
+// With dtau non-null the node kernel also writes the local pseudo-time steps of the stage
+// input at pseudo-time CFL number cfl_tau (dual time stepping).
 int run_stage(les_ctx* c, const double* q, int mode, double* out, const double* q0,
-              double alpha, hipStream_t s, double cfl = 0.0) {
+              double alpha, hipStream_t s, double cfl = 0.0, double* dtau = nullptr,
+              double cfl_tau = 0.0) {
   StageArgs A = stage_args(c, q);
   A.mode = mode;
   A.out = out;
@@ -659,6 +642,8 @@ int run_stage(les_ctx* c, const double* q, int mode, double* out, const double* 
     A.dtpart = c->d_dtpart;
     A.flag = c->d_flag;
   }
+  A.dtau_out = dtau;
+  A.cfl_tau = cfl_tau;
   if (c->params.closure == LES_MLP) {  // the closure evaluated inside the node kernel
     A.mlp_fused = 1;
     A.mlp.theta = c->mlp_theta;
@@ -952,12 +937,12 @@ int les_dual_step(les_ctx* c, double* q, double* q_prev, int nsteps, double dt, 
                  a2 = have_prev ? 0.5 : 0.0;
     HIP_TRY(c, hipMemcpyAsync(c->dual_qn, q, bytes, hipMemcpyDeviceToDevice, s));
     for (int it = 0; it < subiters; ++it) {
-      hipLaunchKernelGGL(k_local_dtau, dim3(grid_for(N)), dim3(kBlock), 0, s, D, c->phys, q, c->S,
-                         c->jinv, cfl_tau, c->dual_dtau);
       const double* in = q;
       for (int l = 0; l < 5; ++l) {
         double* outb = (l == 4) ? q : ((l % 2 == 0) ? c->qa : c->qb);
-        int rc = run_stage(c, in, 0, c->dual_rhs, nullptr, 0.0, s);
+        // the first stage's node kernel also forms the iteration's local pseudo-time steps
+        int rc = run_stage(c, in, 0, c->dual_rhs, nullptr, 0.0, s, 0.0,
+                           l == 0 ? c->dual_dtau : nullptr, cfl_tau);
         if (rc) return rc;
         DualArgs A;
         A.D = D;
