@@ -58,3 +58,13 @@ def test_oversized_grid_is_rejected_before_any_device_call():
                                    ctypes.byref(h))
             assert rc == lesmi.LES_EINVAL
             assert not h.value
+
+
+def test_missing_library_fails_loudly(monkeypatch, tmp_path):
+    """Without the built library the binding raises at once: there is no fallback path that
+    would compute anything elsewhere."""
+    import pytest
+    monkeypatch.setattr(lesmi, "LIB_PATH", str(tmp_path / "liblesmi.so"))
+    monkeypatch.setattr(lesmi, "_lib", None)
+    with pytest.raises(RuntimeError, match="is not built"):
+        lesmi.load()
