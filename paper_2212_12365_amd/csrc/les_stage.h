@@ -33,7 +33,8 @@ struct StageArgs {
   int mixed;
   const float* S32;    // [9][N]
   float* rec32;        // [kRecCount][N]
-  // k_stage output: mode 0 -> residual into out; mode 1 -> out = q0 - alpha dt J RHS.
+  // k_stage output: mode 0 -> residual into out; mode 1 -> out = q0 - alpha dt J RHS;
+  // mode 2 -> the dual-time update below.
   int mode;
   double* out;
   const double* q0;
@@ -50,6 +51,13 @@ struct StageArgs {
   // and 0 elsewhere.
   double* dtau_out;
   double cfl_tau;
+  // Dual time stepping's point-implicit update fused into the face kernel (mode 2, default
+  // launch shapes): out = [q0 - alpha dtau (J RHS + hist/dt)] / (1 + alpha dtau a0/dt) at
+  // updated nodes, hist = a1 Q^n + a2 Q^(n-1) (Q^(n-1) read only when a2 != 0).
+  const double* dual_qn;
+  const double* dual_qm;
+  const double* dual_dtau;
+  double dual_a0, dual_a1, dual_a2, dual_dt;
   int tile;   // k_stage_planes tile shape, index into kTileNames
   int kmin;   // smallest z-chunk depth (0 = default)
   // Learned closure (k_nodes): inputs [6][N], scale rho Delta^2 |S| [N] and |S| [N] of the
@@ -66,6 +74,8 @@ struct StageArgs {
 };
 
 constexpr int kNumTiles = 10;
+// Default launch shapes (indices into kTileNames): 16x16 in FP64, 32x8 in the mixed form.
+constexpr int kDefaultTileFp64 = 3, kDefaultTileMixed = 0;
 extern const char* const kTileNames[kNumTiles];
 
 hipError_t launch_nodes(const StageArgs& A, hipStream_t s);

@@ -649,13 +649,30 @@ __device__ __forceinline__ void face_eval(const NA& a, const NB& b, const R* Wm,
 // stage update Q = Q0 - alpha dt J R (mode 1). Nodes that are not updated get a zero
 // residual in mode 0 and are left alone in mode 1. pq and pj, when given, are the node's
 // Q0 and J loaded earlier by the caller.
-template <typename R>
+template <typename R, bool kDual = false>
 __device__ __forceinline__ void finish_node(const StageArgs& A, int i, int j, int k,
                                             const R* part, const R* hu, const R* hd,
-                                            const double* pq = nullptr, double pj = 0.0) {
+                                            const double* pq = nullptr, double pj = 0.0,
+                                            double pt = 0.0) {
   const Dims& D = A.D;
   const int N = (int)D.N;
   const int o = i + D.n[0] * (j + D.n[1] * k);
+  if constexpr (kDual) {  // mode 2; pt is the node's pseudo-time step when pq is given
+    if (!is_updated(D, i, j, k)) return;
+    const double J = pq ? pj : A.jac[o], dtau = pq ? pt : A.dual_dtau[o];
+    const double den = 1.0 + A.alpha * dtau * A.dual_a0 / A.dual_dt;
+#pragma unroll
+    for (int c = 0; c < 5; ++c) {
+      R rr = part[c];
+      rr += hu[c] - hd[c];
+      const int e = c * N + o;
+      const double jr = J * (double)rr;
+      const double hist = A.dual_a2 != 0.0 ? A.dual_a1 * A.dual_qn[e] + A.dual_a2 * A.dual_qm[e]
+                                           : A.dual_a1 * A.dual_qn[e];
+      A.out[e] = ((pq ? pq[c] : A.q0[e]) - A.alpha * dtau * (jr + hist / A.dual_dt)) / den;
+    }
+    return;
+  }
   if (is_updated(D, i, j, k)) {
     double fac = 0.0;
     if (A.mode == 1) fac = A.alpha * A.dt[0] * (pq ? pj : A.jac[o]);
@@ -682,7 +699,7 @@ __device__ __forceinline__ void finish_node(const StageArgs& A, int i, int j, in
 // comes from LDS and its lower node from registers (taken from LDS one plane earlier), so the
 // update of the column's node on plane k-1 completes one plane late. The faces below the
 // first and above the last plane of the chunk read their outer node from global memory.
-template <int TX, int TY, typename R>
+template <int TX, int TY, typename R, bool kDual = false>
 __device__ __forceinline__ void stage_block(const StageArgs& A, int bx, int by, int kbeg,
                                             int kend, PlaneLds<TX, TY, R>& L) {
   using PL = PlaneLds<TX, TY, R>;
@@ -834,12 +851,13 @@ __device__ __forceinline__ void stage_block(const StageArgs& A, int bx, int by, 
     R zl[2] = {0, 0}, wp[5] = {0, 0, 0, 0, 0};
     // Q^(0) and J of the pending node for its stage update, loaded with the staging so that
     // their latency is hidden behind it rather than exposed after the zeta face.
-    double pq[5] = {0, 0, 0, 0, 0}, pj = 0.0;
-    if (pending && A.mode == 1) {
+    double pq[5] = {0, 0, 0, 0, 0}, pj = 0.0, pt = 0.0;
+    if (pending && (kDual || A.mode == 1)) {
       const unsigned o1 = (unsigned)(i + ni * (j + nj * (k - 1)));
 #pragma unroll
       for (int c = 0; c < 5; ++c) pq[c] = A.q0[c * N + o1];
       pj = A.jac[o1];
+      if constexpr (kDual) pt = A.dual_dtau[o1];
     }
     {
       R vw[MW][11], vf[sNF], vdx[MDX][2], vdy[MDY][2];
@@ -904,7 +922,7 @@ __device__ __forceinline__ void stage_block(const StageArgs& A, int bx, int by, 
       const LdsNode<TX, TY, 2, R> nb{L, own1, own2, zl[0], zl[1]};
       R hz[5];
       face_eval<2, R>(lo, nb, Wm, wp, k - 1, nk, true, Ph, hz);
-      finish_node<R>(A, i, j, k - 1, part, hz, hz_lo, pq, pj);
+      finish_node<R, kDual>(A, i, j, k - 1, part, hz, hz_lo, pq, pj, pt);
 #pragma unroll
       for (int c = 0; c < 5; ++c) {
         hz_lo[c] = hz[c];
@@ -1011,7 +1029,7 @@ __device__ __forceinline__ void stage_block(const StageArgs& A, int bx, int by, 
 #pragma unroll
     for (int c = 0; c < 5; ++c) wp[c] = node_state<R>(A, o2).W[c];
     face_eval<2, R>(lo, nb, Wm, wp, kend - 1, nk, true, Ph, hz);
-    finish_node<R>(A, i, j, kend - 1, part, hz, hz_lo);
+    finish_node<R, kDual>(A, i, j, kend - 1, part, hz, hz_lo);
   }
 }
 
@@ -1027,7 +1045,8 @@ constexpr int min_waves() {
   return want < lds ? want : (lds > 1 ? lds : 1);
 }
 
-template <int TX, int TY, int WPE, typename R>
+// kDual: the dual-time update (mode 2) in place of the residual or Runge-Kutta epilogue.
+template <int TX, int TY, int WPE, typename R, bool kDual = false>
 __global__ void __launch_bounds__(TX * TY) __attribute__((amdgpu_waves_per_eu(WPE, 8)))
 k_stage_planes(StageArgs A, int kchunk) {
   __shared__ PlaneLds<TX, TY, R> L;
@@ -1036,7 +1055,7 @@ k_stage_planes(StageArgs A, int kchunk) {
   const int t = xcd_tile(lin, gx * gy * gridDim.z);
   const int bx = t % gx, by = (t / gx) % gy, bz = t / (gx * gy);
   const int kbeg = bz * kchunk;
-  stage_block<TX, TY, R>(A, bx, by, kbeg, min(kbeg + kchunk, A.D.n[2]), L);
+  stage_block<TX, TY, R, kDual>(A, bx, by, kbeg, min(kbeg + kchunk, A.D.n[2]), L);
 }
 
 // Persistent form over the members of a batch: item = (member, bx | by << 16, kbeg, kend).
@@ -1110,14 +1129,15 @@ const char* const kTileNames[kNumTiles] = {"32x8", "32x4", "16x8", "16x16", "16x
                                            "16x16/w2", "32x8/w3", "16x16/w3", "32x8/w4",
                                            "16x16/w4"};
 
-template <int TX, int TY, int WPE = 1, typename R = double>
+template <int TX, int TY, int WPE = 1, typename R = double, bool kDual = false>
 hipError_t launch_planes(const StageArgs& A, hipStream_t s, int kmin) {
   const int gx = (A.D.n[0] + TX - 1) / TX, gy = (A.D.n[1] + TY - 1) / TY;
   // Blocks resident at once on the device (occupancy query, kept after the first call).
   static int resident = 0;
   if (resident <= 0) {
     int per_cu = 0, dev = 0, cus = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_stage_planes<TX, TY, WPE, R>,
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu,
+                                                     k_stage_planes<TX, TY, WPE, R, kDual>,
                                                      TX * TY, 0) == hipSuccess &&
         hipGetDevice(&dev) == hipSuccess &&
         hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess)
@@ -1125,7 +1145,8 @@ hipError_t launch_planes(const StageArgs& A, hipStream_t s, int kmin) {
   }
   const int kchunk = kchunk_for(A.D, TX, TY, kmin, resident);
   const int nz = (A.D.n[2] + kchunk - 1) / kchunk;
-  hipLaunchKernelGGL((k_stage_planes<TX, TY, WPE, R>), dim3(gx, gy, nz), dim3(TX * TY), 0, s, A, kchunk);
+  hipLaunchKernelGGL((k_stage_planes<TX, TY, WPE, R, kDual>), dim3(gx, gy, nz), dim3(TX * TY), 0,
+                     s, A, kchunk);
   return hipGetLastError();
 }
 
@@ -1222,6 +1243,12 @@ hipError_t launch_nodes_batch(const BatchLaunch& B, hipStream_t s) {
 
 hipError_t launch_stage(const StageArgs& A, hipStream_t s) {
   const int kmin = A.kmin > 0 ? A.kmin : 8;
+  if (A.mode == 2) {  // the dual-time update: default launch shapes only
+    if (A.tile != (A.mixed ? kDefaultTileMixed : kDefaultTileFp64)) return hipErrorInvalidValue;
+    // (the mixed form asks for 3 waves/EU: its longer epilogue would otherwise cost one)
+    return A.mixed ? launch_planes<32, 8, 3, float, true>(A, s, kmin)
+                   : launch_planes<16, 16, 1, double, true>(A, s, kmin);
+  }
   if (A.mixed) switch (A.tile) {
       case 1: return launch_planes<32, 4, 1, float>(A, s, kmin);
       case 2: return launch_planes<16, 8, 1, float>(A, s, kmin);

@@ -627,11 +627,20 @@ int prof_mark(les_ctx* c, hipStream_t s) {
 // residual (mode 0) or the Runge-Kutta stage update (mode 1) as the epilogue.
 // With cfl > 0, the node kernel also reduces the time step of this stage's input (its block
 // minima, then k_dt_final) before the face kernel uses it.
+// Terms of the dual-time update fused into the face kernel (mode 2).
+struct DualStage {
+  const double* qn;
+  const double* qm;
+  const double* dtau;
+  double a0, a1, a2, dt;
+};
+
 // With dtau non-null the node kernel also writes the local pseudo-time steps of the stage
-// input at pseudo-time CFL number cfl_tau (dual time stepping).
+// input at pseudo-time CFL number cfl_tau (dual time stepping); mode 2 takes the dual-time
+// update's terms from dual.
 int run_stage(les_ctx* c, const double* q, int mode, double* out, const double* q0,
               double alpha, hipStream_t s, double cfl = 0.0, double* dtau = nullptr,
-              double cfl_tau = 0.0) {
+              double cfl_tau = 0.0, const DualStage* dual = nullptr) {
   StageArgs A = stage_args(c, q);
   A.mode = mode;
   A.out = out;
@@ -644,6 +653,15 @@ int run_stage(les_ctx* c, const double* q, int mode, double* out, const double* 
   }
   A.dtau_out = dtau;
   A.cfl_tau = cfl_tau;
+  if (dual) {
+    A.dual_qn = dual->qn;
+    A.dual_qm = dual->qm;
+    A.dual_dtau = dual->dtau;
+    A.dual_a0 = dual->a0;
+    A.dual_a1 = dual->a1;
+    A.dual_a2 = dual->a2;
+    A.dual_dt = dual->dt;
+  }
   if (c->params.closure == LES_MLP) {  // the closure evaluated inside the node kernel
     A.mlp_fused = 1;
     A.mlp.theta = c->mlp_theta;
@@ -749,7 +767,7 @@ int les_init_grid(const les_params* params, const double* xyz, les_ctx** out) {
   c->dims = D;
   c->phys = make_phys(*params);
   // Stage kernel launch shape: the fastest measured on the 256 x 128 x 128 jet.
-  c->tile = params->precision == LES_MIXED ? 0 : 3;
+  c->tile = params->precision == LES_MIXED ? kDefaultTileMixed : kDefaultTileFp64;
   c->n_updated = 1;
   for (int d = 0; d < 3; ++d) c->n_updated *= D.per[d] ? D.n[d] : D.n[d] - 2;
   if (hipGetDevice(&c->device) != hipSuccess) {
@@ -932,14 +950,28 @@ int les_dual_step(les_ctx* c, double* q, double* q_prev, int nsteps, double dt, 
   if (chunk < 1024) chunk = 1024;
   const int nparts = (int)((N + chunk - 1) / chunk);
   hipLaunchKernelGGL(k_set_int, dim3(1), dim3(1), 0, s, c->d_flag, 0);
+  // Stages 2-5 take the update in the face kernel's epilogue (its default launch shapes);
+  // the first stage keeps the separate update, which also forms the residual monitor.
+  const bool fused =
+      c->tile == (c->params.precision == LES_MIXED ? kDefaultTileMixed : kDefaultTileFp64);
   for (int n = 0; n < nsteps; ++n) {
     const double a0 = have_prev ? 1.5 : 1.0, a1 = have_prev ? -2.0 : -1.0,
                  a2 = have_prev ? 0.5 : 0.0;
+    const DualStage ds{c->dual_qn, have_prev ? c->dual_qm : c->dual_qn, c->dual_dtau, a0, a1,
+                       a2, dt};
     HIP_TRY(c, hipMemcpyAsync(c->dual_qn, q, bytes, hipMemcpyDeviceToDevice, s));
     for (int it = 0; it < subiters; ++it) {
       const double* in = q;
       for (int l = 0; l < 5; ++l) {
         double* outb = (l == 4) ? q : ((l % 2 == 0) ? c->qa : c->qb);
+        if (l > 0 && fused) {  // the update in the face kernel's epilogue
+          int rc = run_stage(c, in, 2, outb, q, kAlpha[l], s, 0.0, nullptr, 0.0, &ds);
+          if (rc) return rc;
+          rc = run_bc(c, outb, s);
+          if (rc) return rc;
+          in = outb;
+          continue;
+        }
         // the first stage's node kernel also forms the iteration's local pseudo-time steps
         int rc = run_stage(c, in, 0, c->dual_rhs, nullptr, 0.0, s, 0.0,
                            l == 0 ? c->dual_dtau : nullptr, cfl_tau);
