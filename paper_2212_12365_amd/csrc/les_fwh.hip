@@ -240,10 +240,30 @@ __global__ void __launch_bounds__(kFwhBlock)
       if (ok[u] && (!ok[u - 1] || d < 0 || d > 1)) regular = false;
     }
     if (regular) {
-      double gn[kFwhTimes];
+      // Row m_u + 1 is gathered only by the lanes whose interval changed at u (the others
+      // take g_{m_u + 1} from u - 1): all gathers are issued before any of them is used.
+      double v[kFwhTimes][7], gn[kFwhTimes];
       const double g0 = g_at(mu[0]);
 #pragma unroll
-      for (int u = 0; u < kFwhTimes; ++u) gn[u] = g_at(mu[u] + 1);
+      for (int u = 0; u < kFwhTimes; ++u)
+        if (u == 0 || mu[u] != mu[u - 1]) {
+          const double* sm = src + (size_t)(mu[u] + 1) * 7 * ns + s;
+#pragma unroll
+          for (int c = 0; c < 7; ++c) v[u][c] = sm[(size_t)c * ns];
+        }
+#pragma unroll
+      for (int u = 0; u < kFwhTimes; ++u) {
+        if (u == 0 || mu[u] != mu[u - 1]) {
+          double g = cq * v[u][0];
+#pragma unroll
+          for (int c = 0; c < 3; ++c) g = fma(cl[c], v[u][1 + c], g);
+#pragma unroll
+          for (int c = 0; c < 3; ++c) g = fma(cd[c], v[u][4 + c], g);
+          gn[u] = g;
+        } else {
+          gn[u] = gn[u - 1];
+        }
+      }
       double g_lo = g0;
 #pragma unroll
       for (int u = 0; u < kFwhTimes; ++u) {
