@@ -91,23 +91,109 @@ __device__ double diff_rule(const Dims& D, int e, const int* ix, F value) {
   return 0.5 * (3.0 * value(a) - 4.0 * value(b) + value(c));
 }
 
-__global__ void k_metrics(MetricArgs A, double* __restrict__ S, double* __restrict__ jinv) {
+// J^-1 = det[r_xi, r_eta, r_zeta] and the conservative metrics
+// S_d^c = delta_{d+2}(x_{c+2} delta_{d+1} x_{c+1}) - delta_{d+1}(x_{c+2} delta_{d+2} x_{c+1}),
+// r_e and delta by the difference rule (centred, one-sided at the ends of a non-periodic
+// direction), one thread per node, in two kernels over the grid. k_metrics_inner takes the
+// nodes away from those ends: they use only centred differences, whose nested stencil lies
+// in the node's 3 x 3 x 3 neighbourhood less the corners, so those 19 coordinates are loaded
+// once into registers and the same operations, in the same order, run on them.
+// k_metrics_edge takes the nodes at a non-periodic end, each coordinate from memory as the
+// rules ask.
+__device__ __forceinline__ bool metrics_inner(const Dims& D, const int* ix) {
+  bool in = true;
+#pragma unroll
+  for (int e = 0; e < 3; ++e) in = in && (D.per[e] || (ix[e] > 0 && ix[e] < D.n[e] - 1));
+  return in;
+}
+
+__device__ __forceinline__ int cube_t(int a, int b, int g) {
+  return (a + 1) + 3 * (b + 1) + 9 * (g + 1);
+}
+
+// Index into the 3 x 3 x 3 neighbourhood of the offset s e_u + q e_v.
+__device__ __forceinline__ int cube_at(int u, int s, int v, int q) {
+  int o[3] = {0, 0, 0};
+  o[u] += s;
+  o[v] += q;
+  return cube_t(o[0], o[1], o[2]);
+}
+
+__global__ void __launch_bounds__(256)
+    k_metrics_inner(const double* __restrict__ xyz, Dims D, Shift sh, double* __restrict__ S,
+                    double* __restrict__ jinv) {
+  const long long id = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (id >= D.N) return;
+  const int i = (int)(id % D.n[0]);
+  const int j = (int)((id / D.n[0]) % D.n[1]);
+  const int k = (int)(id / ((long long)D.n[0] * D.n[1]));
+  const int ix[3] = {i, j, k};
+  if (!metrics_inner(D, ix)) return;
+  double X[3][27];  // coordinate c at offset (a, b, g), index cube_t(a, b, g)
+#pragma unroll
+  for (int t = 0; t < 27; ++t) {
+    const int o[3] = {t % 3 - 1, (t / 3) % 3 - 1, t / 9 - 1};
+    if (o[0] != 0 && o[1] != 0 && o[2] != 0) continue;  // corners: not in the stencil
+    // the node index across a periodic wrap, and the period translation added per wrap
+    int q[3];
+    double add[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+      q[d] = ix[d] + o[d];
+      if (q[d] < 0) {
+        q[d] += D.n[d];
+        for (int c = 0; c < 3; ++c) add[c] -= sh.s[d][c];
+      } else if (q[d] >= D.n[d]) {
+        q[d] -= D.n[d];
+        for (int c = 0; c < 3; ++c) add[c] += sh.s[d][c];
+      }
+    }
+    const long long n = nid(D, q[0], q[1], q[2]);
+#pragma unroll
+    for (int c = 0; c < 3; ++c) X[c][t] = xyz[(long long)c * D.N + n] + add[c];
+  }
+  double r[3][3];  // r[e][c] = delta_e x_c
+#pragma unroll
+  for (int e = 0; e < 3; ++e)
+#pragma unroll
+    for (int c = 0; c < 3; ++c)
+      r[e][c] = 0.5 * (X[c][cube_at(e, 1, e, 0)] - X[c][cube_at(e, -1, e, 0)]);
+  jinv[id] = r[0][0] * (r[1][1] * r[2][2] - r[2][1] * r[1][2]) -
+             r[1][0] * (r[0][1] * r[2][2] - r[2][1] * r[0][2]) +
+             r[2][0] * (r[0][1] * r[1][2] - r[1][1] * r[0][2]);
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    const int d1 = (d + 1) % 3, d2 = (d + 2) % 3;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      const int c1 = (c + 1) % 3, c2 = (c + 2) % 3;
+      // x_c2 delta_in x_c1 at the offset s along out
+      auto prod = [&](int out, int s, int in) {
+        const double dx = 0.5 * (X[c1][cube_at(out, s, in, 1)] - X[c1][cube_at(out, s, in, -1)]);
+        return X[c2][cube_at(out, s, in, 0)] * dx;
+      };
+      const double t1 = 0.5 * (prod(d2, 1, d1) - prod(d2, -1, d1));
+      const double t2 = 0.5 * (prod(d1, 1, d2) - prod(d1, -1, d2));
+      S[(long long)(3 * d + c) * D.N + id] = t1 - t2;
+    }
+  }
+}
+
+__global__ void k_metrics_edge(MetricArgs A, double* __restrict__ S, double* __restrict__ jinv) {
   long long id = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (id >= A.D.N) return;
   int i = (int)(id % A.D.n[0]);
   int j = (int)((id / A.D.n[0]) % A.D.n[1]);
   int k = (int)(id / ((long long)A.D.n[0] * A.D.n[1]));
   int ix[3] = {i, j, k};
+  if (metrics_inner(A.D, ix)) return;
   double r[3][3];  // r[e][c] = delta_e x_c
   for (int e = 0; e < 3; ++e)
     for (int c = 0; c < 3; ++c)
       r[e][c] = diff_rule(A.D, e, ix, [&](const int* p) { return coord(A, c, p[0], p[1], p[2]); });
-  // J^-1 = det[r_xi, r_eta, r_zeta].
   jinv[id] = r[0][0] * (r[1][1] * r[2][2] - r[2][1] * r[1][2]) -
              r[1][0] * (r[0][1] * r[2][2] - r[2][1] * r[0][2]) +
              r[2][0] * (r[0][1] * r[1][2] - r[1][1] * r[0][2]);
-  // Conservative metrics: S_d^c = delta_{d+2}(x_{c+2} delta_{d+1} x_{c+1})
-  //                             - delta_{d+1}(x_{c+2} delta_{d+2} x_{c+1}).
   for (int d = 0; d < 3; ++d) {
     int d1 = (d + 1) % 3, d2 = (d + 2) % 3;
     for (int c = 0; c < 3; ++c) {
@@ -824,7 +910,9 @@ int les_init_grid(const les_params* params, const double* xyz, les_ctx** out) {
   A.D = D;
   for (int d = 0; d < 3; ++d)
     for (int e = 0; e < 3; ++e) A.sh.s[d][e] = params->period_shift[d][e];
-  hipLaunchKernelGGL(k_metrics, dim3(grid_for(N)), dim3(kBlock), 0, 0, A, c->S, c->jinv);
+  hipLaunchKernelGGL(k_metrics_inner, dim3(grid_for(N)), dim3(kBlock), 0, 0, A.xyz, A.D, A.sh,
+                     c->S, c->jinv);  // kBlock = 256, the kernel's launch bound
+  hipLaunchKernelGGL(k_metrics_edge, dim3(grid_for(N)), dim3(kBlock), 0, 0, A, c->S, c->jinv);
   hipLaunchKernelGGL(k_set_int, dim3(1), dim3(1), 0, 0, c->d_flag, 0);
   hipLaunchKernelGGL(k_jacobian, dim3(grid_for(N)), dim3(kBlock), 0, 0, D, c->jinv, c->jac,
                      c->d_flag);
