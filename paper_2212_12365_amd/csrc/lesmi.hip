@@ -179,14 +179,45 @@ __global__ void __launch_bounds__(256)
   }
 }
 
-__global__ void k_metrics_edge(MetricArgs A, double* __restrict__ S, double* __restrict__ jinv) {
-  long long id = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (id >= A.D.N) return;
-  int i = (int)(id % A.D.n[0]);
-  int j = (int)((id / A.D.n[0]) % A.D.n[1]);
-  int k = (int)(id / ((long long)A.D.n[0] * A.D.n[1]));
-  int ix[3] = {i, j, k};
-  if (metrics_inner(A.D, ix)) return;
+// Nodes on the ends of the non-periodic directions: direction 0's two end planes, then
+// direction 1's without the nodes already taken, then direction 2's.
+__host__ __device__ inline long long edge_count(const Dims& D) {
+  long long m[3] = {D.n[0], D.n[1], D.n[2]}, c = 0;
+  for (int e = 0; e < 3; ++e) {
+    if (D.per[e]) continue;
+    c += 2 * m[(e + 1) % 3] * m[(e + 2) % 3];
+    m[e] -= 2;
+  }
+  return c;
+}
+
+// Index of edge node t (0 <= t < edge_count(D)).
+__device__ __forceinline__ void edge_node(const Dims& D, long long t, int* ix) {
+  int lo[3] = {0, 0, 0}, hi[3] = {D.n[0] - 1, D.n[1] - 1, D.n[2] - 1};
+  for (int e = 0; e < 3; ++e) {
+    if (D.per[e]) continue;
+    const int f = e == 0 ? 1 : 0, g = e == 2 ? 1 : 2;  // the other two, in order
+    const long long lf = hi[f] - lo[f] + 1, face = lf * (hi[g] - lo[g] + 1);
+    if (t < 2 * face) {
+      const long long r = t % face;
+      ix[e] = t < face ? lo[e] : hi[e];
+      ix[f] = lo[f] + (int)(r % lf);
+      ix[g] = lo[g] + (int)(r / lf);
+      return;
+    }
+    t -= 2 * face;
+    ++lo[e];
+    --hi[e];
+  }
+}
+
+__global__ void k_metrics_edge(MetricArgs A, long long count, double* __restrict__ S,
+                               double* __restrict__ jinv) {
+  const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= count) return;
+  int ix[3];
+  edge_node(A.D, t, ix);
+  const long long id = nid(A.D, ix[0], ix[1], ix[2]);
   double r[3][3];  // r[e][c] = delta_e x_c
   for (int e = 0; e < 3; ++e)
     for (int c = 0; c < 3; ++c)
@@ -912,7 +943,10 @@ int les_init_grid(const les_params* params, const double* xyz, les_ctx** out) {
     for (int e = 0; e < 3; ++e) A.sh.s[d][e] = params->period_shift[d][e];
   hipLaunchKernelGGL(k_metrics_inner, dim3(grid_for(N)), dim3(kBlock), 0, 0, A.xyz, A.D, A.sh,
                      c->S, c->jinv);  // kBlock = 256, the kernel's launch bound
-  hipLaunchKernelGGL(k_metrics_edge, dim3(grid_for(N)), dim3(kBlock), 0, 0, A, c->S, c->jinv);
+  const long long ne = edge_count(D);
+  if (ne > 0)
+    hipLaunchKernelGGL(k_metrics_edge, dim3(grid_for(ne)), dim3(kBlock), 0, 0, A, ne, c->S,
+                       c->jinv);
   hipLaunchKernelGGL(k_set_int, dim3(1), dim3(1), 0, 0, c->d_flag, 0);
   hipLaunchKernelGGL(k_jacobian, dim3(grid_for(N)), dim3(kBlock), 0, 0, D, c->jinv, c->jac,
                      c->d_flag);
