@@ -113,6 +113,7 @@ struct les_batch {
   int tile = 0, kmin = 8;
   int cus = 256;
   int occ_nodes = 1, occ_faces = 1;  // resident blocks per CU of the two stage kernels
+  int occ_bc = 1;                     // and of the boundary kernel
   std::string err;
 
   StageArgs* d_args = nullptr;  // [kRows][n]
@@ -296,7 +297,9 @@ int enqueue_stage_kernels(les_batch* b, int row, hipStream_t s, double cfl = 0.0
 // One Runge-Kutta step of every member on stream s (no host synchronisation).
 int enqueue_step(les_batch* b, double cfl, double dt_fixed, hipStream_t s) {
   const int n = (int)b->m.size();
-  const int small = persistent_grid(b, 4, b->nwbc);
+  // no more blocks than are resident at once: a block beyond them would start its items only
+  // after a resident block had finished all of its own
+  const int small = persistent_grid(b, b->occ_bc, b->nwbc);
   if (!(cfl > 0.0))
     hipLaunchKernelGGL(k_batch_set_dt, dim3((n + 63) / 64), dim3(64), 0, s, b->d_mem, n, dt_fixed);
   int rc = check_launch(b, "batch time step");
@@ -374,6 +377,10 @@ int les_batch_create(les_ctx* const* members, int n, les_batch** out) {
           hipSuccess &&
       cus > 0)
     b->cus = cus;
+  int occ = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, k_batch_bc, 256, 0) == hipSuccess &&
+      occ > 0)
+    b->occ_bc = occ;
   int rc = build_static_work(b);
   if (!rc) rc = build_face_work(b);
   if (!rc && hipMalloc((void**)&b->d_args, (size_t)kRows * n * sizeof(StageArgs)) != hipSuccess)
