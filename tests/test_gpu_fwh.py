@@ -187,3 +187,46 @@ def test_fwh_ragged_groups_skipped_times_and_errors(torch):
         FWH(cb, xb, 1, 4, 2, caps=3, capacity=8, dtau=dtau)
     assert e.value.code == LES_EINVAL
     cb.close()
+
+
+def test_fwh_time_grouping_and_order_do_not_change_the_result(torch):
+    """The kernel takes a group of 8 observer times per block and, when their retarded
+    times advance by at most one sample interval each, gathers the group's sample rows
+    together (otherwise one change of interval at a time). Every term is the same
+    arithmetic either way and the nodes are summed in the same order, so the pressure at a
+    time is bitwise the same whether the times come in order, reversed, far apart, or one
+    per call."""
+    print("[gpu] Ffowcs Williams-Hawkings: grouping and order of the times", flush=True)
+    from paper_2212_12365_amd.lesmi import FWH, Context
+    n = (48, 32, 16)
+    xyz, _ = jet_grid(n)
+    p = sy.jet_params(n)
+    rho0, c0, p0 = p.rho_inf, 1.0, p.p_inf
+    r_of_j = np.hypot(xyz[1, 0, :, 0], xyz[2, 0, :, 0])
+    x_of_i = xyz[0, 0, 0, :]
+    js = int(np.argmin(np.abs(r_of_j - 1.5)))
+    i1, i2 = int(np.argmin(np.abs(x_of_i - 2.0))), int(np.argmin(np.abs(x_of_i - 6.0)))
+    src = np.array([0.5 * (x_of_i[i1] + x_of_i[i2]), 0.0, 0.0])
+    A, T = 1e-4, 4.0
+    omega, dtau, M = 2 * math.pi / T, T / 16, 48
+    ctx = Context(p, xyz)
+    f = FWH(ctx, xyz, i1, i2, js, caps=3, capacity=M, dtau=dtau)
+    g = torch.empty((5,) + p.shape, dtype=torch.float64, device="cuda")
+    for m in range(M):
+        g.copy_(torch.from_numpy(monopole_state(xyz, src, A, omega, m * dtau, p.gamma, rho0,
+                                                c0, p0)))
+        f.sample(g)
+    D = 12.0
+    dirs = np.array([[1, 0, 0], [0, 1, 0], [-1, 0.5, 0.2]], dtype=np.float64)
+    obs = src[None, :] + D * dirs / np.linalg.norm(dirs, axis=1)[:, None]
+    for spacing in (0.3, 2.5):  # a fraction of a sample apart, and several samples apart
+        times = D / c0 + 1.0 + spacing * dtau * np.arange(20)
+        ref = f.pressure(obs, times, c0, p0)[0].cpu().numpy()
+        rev = f.pressure(obs, times[::-1].copy(), c0, p0)[0].cpu().numpy()
+        np.testing.assert_array_equal(rev[:, ::-1], ref)
+        for b in (0, 7, 8, 19):
+            one = f.pressure(obs, times[b:b + 1], c0, p0)[0].cpu().numpy()
+            np.testing.assert_array_equal(one[:, 0], ref[:, b])
+        assert np.abs(ref).max() > 0
+    f.close()
+    ctx.close()
